@@ -1,0 +1,164 @@
+/*
+ * ck.h -- C ABI of the MI355X (gfx950) batched chemical-kinetics library.
+ *
+ * The library integrates many independent constant-pressure homogeneous
+ * reactors (Stone, Alferman & Niemeyer, arXiv 1608.05794).  Each reactor is
+ * the autonomous ODE system du/dt = f(u) of Section 2 (Eq. ode) with state
+ * u = (T, Y_1 .. Y_n), N = n + 1, and the source term of Section 3
+ * (Eqs. ydot, tdot, wdot, kfor, krev, kc, tfits).
+ *
+ * Conventions for every call below
+ *   - Units are SI: K, Pa, kg/mol, mol/m^3, J/mol, s.
+ *   - States are structure-of-arrays float64: y[i * ld + r] is component i
+ *     (i = 0 temperature, i = 1 + k mass fraction of species k) of reactor r,
+ *     0 <= r < n, ld >= n.  Consecutive reactors are adjacent in memory.
+ *   - All array arguments are DEVICE pointers owned by the caller; the
+ *     library never frees them.  `stream` is a hipStream_t (NULL = the
+ *     null stream).  Calls are asynchronous on that stream; the return code
+ *     covers argument validation and kernel launch only.
+ *   - Return codes: CK_OK or a negative CK_E* value (see ck_strerror).
+ *   - A mechanism handle is immutable after ck_mechanism_load and may be
+ *     used from several streams at once.
+ */
+#ifndef CK_H
+#define CK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ck_mech ck_mech;
+
+enum {
+    CK_OK = 0,
+    CK_EINVAL = -1,        /* bad argument (null pointer, negative size, ld < n, bad tolerance) */
+    CK_EIO = -2,           /* mechanism file cannot be opened */
+    CK_EPARSE = -3,        /* mechanism file malformed */
+    CK_ENOMEM = -4,        /* device or host allocation failed */
+    CK_EHIP = -5,          /* HIP runtime error (launch, copy) */
+    CK_EUNSUPPORTED = -6   /* option combination not implemented for this mechanism size */
+};
+
+/* Per-reactor integration outcome (status[] array). */
+enum {
+    CK_ST_OK = 0,          /* reached t_end */
+    CK_ST_MAX_STEPS = 1,   /* attempted-step budget exhausted before t_end */
+    CK_ST_H_UNDERFLOW = 2, /* step size fell below max(1e-30 s, 16 eps |t|) */
+    CK_ST_NONFINITE = 3    /* initial state or its source term not finite */
+};
+
+/* Kernel choice for the integrators. */
+enum {
+    CK_KERNEL_AUTO = 0,    /* wavefront-per-reactor work queue where supported, else lane-per-reactor */
+    CK_KERNEL_LANE = 1,    /* one reactor per lane, all scratch in global memory (Algorithm 2 analogue) */
+    CK_KERNEL_WAVE = 2     /* one reactor per 64-lane wavefront, persistent work queue */
+};
+
+/* Precision of the Rosenbrock linear solves. */
+enum {
+    CK_PREC_FP64 = 0,      /* FP64 LU and triangular solves */
+    CK_PREC_FP32_REFINE = 1 /* FP32 LU with FP64 residual refinement; wavefront kernel only */
+};
+
+typedef struct {
+    double rtol;           /* relative tolerance, > 0 unless h_fixed > 0 */
+    double atol;           /* absolute tolerance, >= 0 */
+    double h0;             /* > 0: initial step for reactors whose h[] entry is not > 0; 0: estimate */
+    double h_fixed;        /* > 0: fixed-step mode (every step accepted, no control) */
+    int64_t max_steps;     /* attempted (accepted + rejected) steps per reactor and call */
+    int32_t kernel;        /* CK_KERNEL_* */
+    int32_t precision;     /* CK_PREC_* (ROS4 only) */
+    int32_t refine_sweeps; /* FP32 mode: maximum FP64 refinement sweeps, 0..3 */
+    int32_t reserved;
+} ck_opts;
+
+/* Fills *o with the defaults: rtol 1e-8, atol 1e-12, h0 0, h_fixed 0, max_steps 1e6,
+ * CK_KERNEL_AUTO, CK_PREC_FP64, refine_sweeps 3. */
+void ck_opts_default(ck_opts *o);
+
+const char *ck_strerror(int code);
+
+/*
+ * Mechanism staging (Section 3; the paper preprocesses its mechanisms into a
+ * binary database that its source-term code reads).  Parses the text file at
+ * `path` (format: CKMECH 1, written by the package's synth module), packs the
+ * species NASA-7 data and the per-reaction Arrhenius, stoichiometry,
+ * third-body and fall-off parameters, and uploads them to `device`.
+ * On success *out receives a handle; free it with ck_mechanism_free.
+ * Errors: CK_EIO, CK_EPARSE, CK_ENOMEM, CK_EHIP, CK_EINVAL.
+ */
+int ck_mechanism_load(const char *path, int device, ck_mech **out);
+void ck_mechanism_free(ck_mech *m);
+int ck_mechanism_info(const ck_mech *m, int *n_species, int *n_reactions, int *n_elements);
+
+/*
+ * Source term f(y) (Section 3, Eqs. ydot and tdot with Eq. wdot):
+ * dY_k/dt = W_k wdot_k / rho and dT/dt = -sum_k H_k wdot_k / (rho cp), at
+ * constant pressure p[r] (Pa).  y and dydt are [N][ld] (they may not
+ * alias); p is [n].  n = 0 is a no-op.
+ */
+int ck_rhs_eval(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p,
+                double *dydt, void *stream);
+
+/*
+ * Analytic Jacobian J = df/dy of the source term above (the derivative the
+ * paper approximates by forward differences in Section 5; analytic forms are
+ * its recommended improvement).  jac is [N*N][ld]: jac[(i*N + j)*ld + r] =
+ * df_i/dy_j of reactor r, i.e. row-major per reactor, reactor-minor.
+ */
+int ck_jacobian_eval(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p,
+                     double *jac, void *stream);
+
+/*
+ * Bytes of device workspace that ck_integrate_* needs for n reactors with
+ * options o (NULL = defaults).  Pass a buffer at least this large as
+ * `workspace`, or NULL to let the library allocate (and cache) its own.
+ */
+size_t ck_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts *o);
+
+/*
+ * Integrate every reactor from t[r] (0 if t == NULL) to t_end[r] with the
+ * four-stage L-stable Rosenbrock method of Section 2 / Appendix C (ROS4) and
+ * adaptive steps (Algorithm 1 per reactor: EstimateH0, OneStep, accept if the
+ * weighted RMS error < 1, AdjustStepSize).
+ *   y        [N][ld] in/out state.
+ *   p        [n] pressures (Pa).
+ *   t_end    [n] end times.
+ *   t, h     optional [n] in/out: start time / last proposed step; pass them
+ *            back to resume exactly where a call stopped.  h[r] > 0 on input
+ *            is used as the first step.
+ *   status, n_accept, n_reject   [n] outputs (int32).
+ *   workspace  device buffer of ck_workspace_bytes(), or NULL.
+ * A reactor whose status is not CK_ST_OK keeps its last accepted (t, h, y).
+ */
+int ck_integrate_ros4(const ck_mech *m, int64_t n, double *y, int64_t ld, const double *p,
+                      const double *t_end, double *t, double *h, const ck_opts *o, void *workspace,
+                      int32_t *status, int32_t *n_accept, int32_t *n_reject, void *stream);
+
+/* Same contract with the embedded Runge--Kutta--Fehlberg 4(5) pair of
+ * Section 2 / Appendix B (fourth-order solution propagated). */
+int ck_integrate_rkf45(const ck_mech *m, int64_t n, double *y, int64_t ld, const double *p,
+                       const double *t_end, double *t, double *h, const ck_opts *o, void *workspace,
+                       int32_t *status, int32_t *n_accept, int32_t *n_reject, void *stream);
+
+/*
+ * Variants of ck_rhs_eval / ck_jacobian_eval with an explicit kernel family
+ * (CK_KERNEL_LANE: one reactor per lane, coalesced; CK_KERNEL_WAVE: one
+ * reactor per wavefront, the family the wavefront integrators use;
+ * CK_KERNEL_AUTO: the library's choice).  ck_rhs_eval uses CK_KERNEL_AUTO
+ * (wavefront); ck_jacobian_eval uses CK_KERNEL_LANE.  CK_KERNEL_WAVE
+ * Jacobians need N <= 64 (CK_EUNSUPPORTED otherwise).  The lane family uses
+ * a library-owned scratch buffer sized for n.
+ */
+int ck_rhs_eval_ex(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
+                   int32_t kernel, void *stream);
+int ck_jacobian_eval_ex(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
+                        int32_t kernel, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CK_H */

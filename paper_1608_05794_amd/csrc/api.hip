@@ -1,0 +1,216 @@
+// C-ABI entry points: argument validation, workspace management and kernel
+// selection.  Every compute step runs in the kernels of k_lane.hip and
+// k_wave.hip.
+#include <climits>
+#include <cmath>
+#include <mutex>
+
+#include "ck_internal.h"
+#include "launch.h"
+
+using namespace ck;
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = (prev == dev) || hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (ok && prev >= 0) hipSetDevice(prev);
+    }
+};
+
+std::mutex g_ws_mutex;
+
+// Library-owned workspace of a mechanism (used when the caller passes none).
+int cached_ws(ck_mech *m, size_t bytes, void **out) {
+    std::lock_guard<std::mutex> lk(g_ws_mutex);
+    if (m->ws_bytes < bytes) {
+        if (m->ws) {
+            hipDeviceSynchronize();
+            hipFree(m->ws);
+            m->ws = nullptr;
+            m->ws_bytes = 0;
+        }
+        if (hipMalloc(&m->ws, bytes) != hipSuccess) return CK_ENOMEM;
+        m->ws_bytes = bytes;
+    }
+    *out = m->ws;
+    return CK_OK;
+}
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+bool check_state_args(const ck_mech *m, int64_t n, const void *y, int64_t ld, const void *p, const void *out) {
+    if (!m || n < 0 || n > INT32_MAX) return false;
+    if (n == 0) return true;
+    return y && p && out && ld >= n;
+}
+
+int validate_opts(const ck_opts *o, IntOpts &io) {
+    ck_opts d;
+    ck_opts_default(&d);
+    if (!o) o = &d;
+    if (!(o->h_fixed >= 0.0) || !(o->h0 >= 0.0)) return CK_EINVAL;
+    if (o->h_fixed == 0.0 && !(o->rtol > 0.0)) return CK_EINVAL;
+    if (!(o->atol >= 0.0) || o->max_steps < 1) return CK_EINVAL;
+    if (o->kernel < CK_KERNEL_AUTO || o->kernel > CK_KERNEL_WAVE) return CK_EINVAL;
+    if (o->precision != CK_PREC_FP64 && o->precision != CK_PREC_FP32_REFINE) return CK_EINVAL;
+    if (o->refine_sweeps < 0 || o->refine_sweeps > 3) return CK_EINVAL;
+    io.rtol = o->rtol;
+    io.atol = o->atol;
+    io.h0 = o->h0;
+    io.h_fixed = o->h_fixed;
+    io.max_steps = o->max_steps;
+    io.precision = o->precision;
+    io.refine_sweeps = o->refine_sweeps;
+    return CK_OK;
+}
+
+// Kernel family an integrate call will use (CK_KERNEL_LANE or CK_KERNEL_WAVE), or an error.
+int choose_kernel(const ck_mech *m, int method, const ck_opts *o) {
+    ck_opts d;
+    ck_opts_default(&d);
+    if (!o) o = &d;
+    const bool wave_ok = wave_supported(m->dev, method, o->precision);
+    if (o->kernel == CK_KERNEL_WAVE || o->kernel == CK_KERNEL_AUTO) {
+        if (wave_ok) return CK_KERNEL_WAVE;
+        if (o->kernel == CK_KERNEL_WAVE || o->precision != CK_PREC_FP64) return CK_EUNSUPPORTED;
+    }
+    if (o->precision != CK_PREC_FP64) return CK_EUNSUPPORTED;
+    return CK_KERNEL_LANE;
+}
+
+size_t lane_bytes(const ck_mech *m, int64_t n, int method) {
+    return size_t(lane_ws_doubles_per_reactor(m->dev, method)) * size_t(round_up(std::max<int64_t>(n, 1), 64)) *
+           sizeof(double);
+}
+
+int integrate(int method, const ck_mech *mc, int64_t n, double *y, int64_t ld, const double *p, const double *t_end,
+              double *t, double *h, const ck_opts *o, void *workspace, int32_t *status, int32_t *nacc, int32_t *nrej,
+              void *stream) {
+    ck_mech *m = const_cast<ck_mech *>(mc);
+    if (!check_state_args(m, n, y, ld, p, y)) return CK_EINVAL;
+    IntOpts io;
+    int rc = validate_opts(o, io);
+    if (rc != CK_OK) return rc;
+    if (n == 0) return CK_OK;
+    if (!t_end || !status || !nacc || !nrej) return CK_EINVAL;
+    const int kern = choose_kernel(m, method, o);
+    if (kern < 0) return kern;
+    DeviceGuard g(m->device);
+    if (!g.ok) return CK_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t need = ck_workspace_bytes(m, n, o);
+    void *ws = workspace;
+    if (!ws) {
+        rc = cached_ws(m, need, &ws);
+        if (rc != CK_OK) return rc;
+    }
+    if (kern == CK_KERNEL_WAVE)
+        return launch_integrate_wave(method, m->dev, n, y, ld, p, t_end, t, h, io, ws, status, nacc, nrej, s);
+    const int64_t S = round_up(n, 64);
+    return launch_integrate_lane(method, m->dev, n, y, ld, p, t_end, t, h, io, static_cast<double *>(ws), S, status,
+                                 nacc, nrej, s);
+}
+
+}  // namespace
+
+extern "C" void ck_opts_default(ck_opts *o) {
+    if (!o) return;
+    o->rtol = 1e-8;
+    o->atol = 1e-12;
+    o->h0 = 0.0;
+    o->h_fixed = 0.0;
+    o->max_steps = 1000000;
+    o->kernel = CK_KERNEL_AUTO;
+    o->precision = CK_PREC_FP64;
+    o->refine_sweeps = 3;
+    o->reserved = 0;
+}
+
+extern "C" const char *ck_strerror(int code) {
+    switch (code) {
+        case CK_OK: return "ok";
+        case CK_EINVAL: return "invalid argument";
+        case CK_EIO: return "cannot open mechanism file";
+        case CK_EPARSE: return "malformed mechanism file";
+        case CK_ENOMEM: return "out of memory";
+        case CK_EHIP: return "HIP runtime error";
+        case CK_EUNSUPPORTED: return "unsupported option for this mechanism";
+        default: return "unknown error";
+    }
+}
+
+extern "C" int ck_rhs_eval_ex(const ck_mech *mc, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
+                              int32_t kernel, void *stream) {
+    ck_mech *m = const_cast<ck_mech *>(mc);
+    if (!check_state_args(m, n, y, ld, p, dydt)) return CK_EINVAL;
+    if (kernel < CK_KERNEL_AUTO || kernel > CK_KERNEL_WAVE) return CK_EINVAL;
+    if (n == 0) return CK_OK;
+    DeviceGuard g(m->device);
+    if (!g.ok) return CK_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (kernel == CK_KERNEL_LANE) {
+        void *ws = nullptr;
+        int rc = cached_ws(m, lane_bytes(m, n, 0), &ws);
+        if (rc != CK_OK) return rc;
+        return launch_rhs_lane(m->dev, n, y, ld, p, dydt, static_cast<double *>(ws), round_up(n, 64), s);
+    }
+    return launch_rhs_wave(m->dev, n, y, ld, p, dydt, s);
+}
+
+extern "C" int ck_rhs_eval(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
+                           void *stream) {
+    return ck_rhs_eval_ex(m, n, y, ld, p, dydt, CK_KERNEL_AUTO, stream);
+}
+
+extern "C" int ck_jacobian_eval_ex(const ck_mech *mc, int64_t n, const double *y, int64_t ld, const double *p,
+                                   double *jac, int32_t kernel, void *stream) {
+    ck_mech *m = const_cast<ck_mech *>(mc);
+    if (!check_state_args(m, n, y, ld, p, jac)) return CK_EINVAL;
+    if (kernel < CK_KERNEL_AUTO || kernel > CK_KERNEL_WAVE) return CK_EINVAL;
+    if (n == 0) return CK_OK;
+    DeviceGuard g(m->device);
+    if (!g.ok) return CK_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (kernel == CK_KERNEL_WAVE) return launch_jac_wave(m->dev, n, y, ld, p, jac, s);
+    void *ws = nullptr;
+    int rc = cached_ws(m, lane_bytes(m, n, 0), &ws);
+    if (rc != CK_OK) return rc;
+    return launch_jac_lane(m->dev, n, y, ld, p, jac, static_cast<double *>(ws), round_up(n, 64), s);
+}
+
+extern "C" int ck_jacobian_eval(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
+                                void *stream) {
+    return ck_jacobian_eval_ex(m, n, y, ld, p, jac, CK_KERNEL_LANE, stream);
+}
+
+extern "C" size_t ck_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts *o) {
+    if (!m || n < 0) return 0;
+    size_t best = 256;
+    for (int method = 0; method < 2; method++) {
+        const int k = choose_kernel(m, method, o);
+        size_t b = 256;
+        if (k == CK_KERNEL_LANE) b = lane_bytes(m, n, method);
+        else if (k == CK_KERNEL_WAVE) b = wave_ws_bytes(m->dev, n);
+        if (b > best) best = b;
+    }
+    return best;
+}
+
+extern "C" int ck_integrate_ros4(const ck_mech *m, int64_t n, double *y, int64_t ld, const double *p,
+                                 const double *t_end, double *t, double *h, const ck_opts *o, void *workspace,
+                                 int32_t *status, int32_t *n_accept, int32_t *n_reject, void *stream) {
+    return integrate(0, m, n, y, ld, p, t_end, t, h, o, workspace, status, n_accept, n_reject, stream);
+}
+
+extern "C" int ck_integrate_rkf45(const ck_mech *m, int64_t n, double *y, int64_t ld, const double *p,
+                                  const double *t_end, double *t, double *h, const ck_opts *o, void *workspace,
+                                  int32_t *status, int32_t *n_accept, int32_t *n_reject, void *stream) {
+    return integrate(1, m, n, y, ld, p, t_end, t, h, o, workspace, status, n_accept, n_reject, stream);
+}

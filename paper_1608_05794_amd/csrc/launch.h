@@ -1,0 +1,36 @@
+// Launchers of the two kernel families (internal to the library).
+#pragma once
+
+#include "ck_internal.h"
+
+namespace ck {
+
+// Integration options as the kernels see them (validated copy of ck_opts).
+struct IntOpts {
+    double rtol, atol, h0, h_fixed;
+    int64_t max_steps;
+    int32_t precision, refine_sweeps;
+};
+
+// lane-per-reactor family (k_lane.hip)
+int64_t lane_ws_doubles_per_reactor(const DevMech &M, int method);
+int launch_rhs_lane(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
+                    double *ws, int64_t wsS, hipStream_t s);
+int launch_jac_lane(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
+                    double *ws, int64_t wsS, hipStream_t s);
+int launch_integrate_lane(int method, const DevMech &M, int64_t n, double *y, int64_t ld, const double *p,
+                          const double *t_end, double *t, double *h, const IntOpts &o, double *ws, int64_t wsS,
+                          int32_t *status, int32_t *nacc, int32_t *nrej, hipStream_t s);
+
+// wavefront-per-reactor family (k_wave.hip)
+bool wave_supported(const DevMech &M, int method, int precision);
+size_t wave_ws_bytes(const DevMech &M, int64_t n);
+int launch_rhs_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
+                    hipStream_t s);
+int launch_jac_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
+                    hipStream_t s);
+int launch_integrate_wave(int method, const DevMech &M, int64_t n, double *y, int64_t ld, const double *p,
+                          const double *t_end, double *t, double *h, const IntOpts &o, void *ws,
+                          int32_t *status, int32_t *nacc, int32_t *nrej, hipStream_t s);
+
+}  // namespace ck

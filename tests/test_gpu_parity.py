@@ -1,0 +1,189 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bars (the library's reading of the target tolerances):
+  - source term: max_k |f_gpu - f_oracle| / D_k <= 1e-12, D_k the gross
+    production + destruction scale of component k (near partial equilibrium
+    the net rates cancel, so a plain relative error is meaningless there);
+  - Jacobian: row-scaled contribution error <= 1e-10;
+  - integration (rtol 1e-8, atol 1e-12): identical statuses, |dT|/T <= 1e-6,
+    and |dy_i| <= 1e-6 (|y_i| + atol/rtol) for every component: the difference
+    measured in the solver's own error weights.  The plain relative error of
+    every Y > 1e-12 is printed too; for species within a few decades of atol it
+    is set by rounding amplification (the oracle against itself with a one-ulp
+    perturbation of y0 shows the same size, see test_oracle_sensitivity.py).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1608_05794_amd import synth
+
+from .parity_util import jac_scaled_error, rhs_scale, state_rel_error, weighted_error
+
+pytestmark = pytest.mark.gpu
+
+RECIPE = {"M13": "small", "M53": "mid", "M111": "divergent"}
+
+
+@pytest.fixture(scope="module")
+def ck():
+    from paper_1608_05794_amd import ck as CK
+    assert torch.cuda.is_available()
+    return CK
+
+
+@pytest.fixture(scope="module")
+def gmech(ck, mech_path):
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            cache[name] = ck.Mechanism(mech_path(name))
+        return cache[name]
+    return get
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+@pytest.mark.parametrize("kernel", ["wave", "lane"])
+@pytest.mark.parametrize("name,n", [("M13", 200), ("M53", 131), ("M111", 70)])
+def test_rhs_parity(ck, gmech, oracle_mech, name, n, kernel):
+    g, om = gmech(name), oracle_mech(name)
+    y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=101)
+    f = ck.rhs(g, dev(y), dev(P), kernel=kernel).cpu().numpy()
+    fo = om.rhs(y, P)
+    D = rhs_scale(om, y, P)
+    err = np.abs(f - fo) / D
+    print(f"[rhs {name} {kernel}] max scaled error {err.max():.3e}", flush=True)
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("kernel", ["lane", "wave"])
+@pytest.mark.parametrize("name,n", [("M13", 70), ("M53", 66), ("M111", 9)])
+def test_jacobian_parity(ck, gmech, oracle_mech, name, n, kernel):
+    g, om = gmech(name), oracle_mech(name)
+    if kernel == "wave" and om.N > 64:
+        pytest.skip("wavefront Jacobian keeps one row per lane: N <= 64")
+    y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=202)
+    J = ck.jac(g, dev(y), dev(P), kernel=kernel).cpu().numpy()          # [N*N, n]
+    J = J.T.reshape(n, om.N, om.N)
+    Jo = om.jac(y, P)
+    err = jac_scaled_error(J, Jo, y)
+    print(f"[jac {name} {kernel}] max scaled error {err:.3e}", flush=True)
+    assert err <= 1e-10
+
+
+def _report_and_check(tag, res, orc):
+    eT, eY = state_rel_error(res["y"], orc["y"])
+    ew = weighted_error(res["y"], orc["y"])
+    steps = res["n_accept"] + res["n_reject"]
+    same = np.mean(steps == orc["n_accept"] + orc["n_reject"])
+    print(f"[{tag}] weighted {ew:.2e}  rel T {eT:.2e}  rel Y(>1e-12) {eY:.2e}  identical step counts {same:.3f}  "
+          f"mean steps {steps.mean():.0f}", flush=True)
+    assert eT <= 1e-6 and ew <= 1e-6
+
+
+def _integrate_both(ck, g, om, y, P, t_end, method, kernel, **kw):
+    res = ck.integrate(g, dev(y), dev(P), t_end, method=method, kernel=kernel, **kw)
+    torch.cuda.synchronize()
+    orc = om.integrate(y, P, t_end, method, **{k: v for k, v in kw.items() if k in ("rtol", "atol", "max_steps",
+                                                                                    "h0", "h_fixed")})
+    return {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in res.items()}, orc
+
+
+@pytest.mark.parametrize("kernel", ["wave", "lane"])
+def test_ros4_parity_small(ck, gmech, oracle_mech, kernel):
+    """Small configuration: M13, P = 1 atm, 1024 reactors, ROS4 to 1e-4 s at rtol 1e-8, atol 1e-12."""
+    g, om = gmech("M13"), oracle_mech("M13")
+    n = 1024 if kernel == "wave" else 128
+    y, P = synth.reactor_states(om.n_species, n, "small", seed=1001)
+    res, orc = _integrate_both(ck, g, om, y, P, 1e-4, "ros4", kernel)
+    assert np.array_equal(res["status"], orc["status"])
+    assert np.all(orc["status"] == 0)
+    _report_and_check(f"ros4 M13 {kernel}", res, orc)
+
+
+@pytest.mark.parametrize("kernel", ["wave", "lane"])
+def test_ros4_parity_mid_sample(ck, gmech, oracle_mech, kernel):
+    """M53 (mid configuration states), a ragged batch of 67 reactors over a shorter horizon."""
+    g, om = gmech("M53"), oracle_mech("M53")
+    y, P = synth.reactor_states(om.n_species, 67, "mid", seed=1002)
+    res, orc = _integrate_both(ck, g, om, y, P, 2e-6, "ros4", kernel)
+    assert np.array_equal(res["status"], orc["status"])
+    _report_and_check(f"ros4 M53 {kernel}", res, orc)
+
+
+@pytest.mark.parametrize("kernel", ["wave", "lane"])
+def test_rkf45_parity(ck, gmech, oracle_mech, kernel):
+    """RKF45 on the small mechanism over a stability-bound horizon (explicit steps ~ 1/rho(J))."""
+    g, om = gmech("M13"), oracle_mech("M13")
+    y, P = synth.reactor_states(om.n_species, 130, "small", seed=1003)
+    res, orc = _integrate_both(ck, g, om, y, P, 2e-12, "rkf45", kernel)
+    assert np.array_equal(res["status"], orc["status"])
+    assert np.all(orc["status"] == 0)
+    _report_and_check(f"rkf45 M13 {kernel}", res, orc)
+
+
+def test_rkf45_parity_m111_two_slots(ck, gmech, oracle_mech):
+    """N > 64: the wavefront RKF45 keeps two state components per lane."""
+    g, om = gmech("M111"), oracle_mech("M111")
+    y, P = synth.reactor_states(om.n_species, 20, "divergent", seed=1004)
+    res, orc = _integrate_both(ck, g, om, y, P, 1e-12, "rkf45", "wave")
+    assert np.array_equal(res["status"], orc["status"])
+    _report_and_check(f"rkf45 M111 wave", res, orc)
+
+
+def test_ros4_m111_lane(ck, gmech, oracle_mech):
+    """N = 112 through the lane kernel (the wavefront ROS4 holds one matrix row per lane, N <= 64)."""
+    g, om = gmech("M111"), oracle_mech("M111")
+    y, P = synth.reactor_states(om.n_species, 5, "divergent", seed=1005)
+    # a fixed budget of 12 attempted steps (the lane kernel is latency-bound at this batch size)
+    res, orc = _integrate_both(ck, g, om, y, P, 1e-3, "ros4", "auto", max_steps=12)
+    assert np.array_equal(res["status"], orc["status"]) and np.all(res["status"] == 1)
+    _report_and_check(f"ros4 M111 auto", res, orc)
+
+
+@pytest.mark.parametrize("method", ["ros4", "rkf45"])
+@pytest.mark.parametrize("kernel", ["wave", "lane"])
+def test_edge_cases(ck, gmech, oracle_mech, method, kernel):
+    g, om = gmech("M13"), oracle_mech("M13")
+    y, P = synth.reactor_states(om.n_species, 65, "small", seed=1006)
+    te = 1e-9 if method == "ros4" else 1e-13
+    # n = 0 is a no-op
+    empty = ck.integrate(g, dev(y[:, :0]), dev(P[:0]), te, method=method, kernel=kernel)
+    assert empty["status"].numel() == 0
+    # non-finite state -> NONFINITE, others unaffected; max_steps -> MAX_STEPS; tiny h0 -> H_UNDERFLOW
+    bad = y.copy()
+    bad[2, 3] = np.nan
+    res, orc = _integrate_both(ck, g, om, bad, P, te, method, kernel)
+    assert res["status"][3] == 3 and np.array_equal(res["status"], orc["status"])
+    res, orc = _integrate_both(ck, g, om, y, P, 1e-5, method, kernel, max_steps=7)
+    assert np.all(res["status"] == 1) and np.all(res["n_accept"] + res["n_reject"] == 7)
+    res, orc = _integrate_both(ck, g, om, y, P, 1e-5, method, kernel, h0=1e-32)
+    assert np.all(res["status"] == 2) and np.array_equal(res["status"], orc["status"])
+    # fixed-step mode: exactly the requested number of steps, same values as the oracle
+    res, orc = _integrate_both(ck, g, om, y, P, 1.6e-14, method, kernel, h_fixed=1e-15)
+    assert np.all(res["n_accept"] == orc["n_accept"])
+    assert weighted_error(res["y"], orc["y"]) <= 1e-9
+
+
+@pytest.mark.parametrize("kernel", ["wave", "lane"])
+def test_resume_and_batch_independence(ck, gmech, kernel):
+    """(t, h, y) resume is bitwise; a reactor's result does not depend on its batch (Section 4: scalar and
+    SIMD results agree)."""
+    g = gmech("M13")
+    y, P = synth.reactor_states(g.n_species, 96, "small", seed=1007)
+    te = 5e-8
+    full = ck.integrate(g, dev(y), dev(P), te, kernel=kernel)
+    t = torch.zeros(96, dtype=torch.float64, device="cuda")
+    h = torch.zeros(96, dtype=torch.float64, device="cuda")
+    part = ck.integrate(g, dev(y), dev(P), te, t=t, h=h, kernel=kernel, max_steps=30)
+    rest = ck.integrate(g, part["y"], dev(P), te, t=t, h=h, kernel=kernel)
+    assert torch.equal(rest["y"], full["y"])
+    assert torch.equal(rest["n_accept"] + part["n_accept"], full["n_accept"])
+    idx = [5, 64, 95]
+    alone = ck.integrate(g, dev(y[:, idx]), dev(P[idx]), te, kernel=kernel)
+    assert torch.equal(alone["y"], full["y"][:, idx])
