@@ -90,12 +90,15 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--mech", default="M53")
     ap.add_argument("--reactors", type=int, default=131072)
     ap.add_argument("--t-end", type=float, default=1e-3)
     ap.add_argument("--kernel", default="wave", choices=["wave", "lane", "auto"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refine"])
+    ap.add_argument("--launch-steps", type=int, default=2000,
+                    help="attempted steps per reactor per kernel launch; launches resume from (t, h)")
+    ap.add_argument("--max-steps", type=int, default=1_000_000, help="attempted steps per reactor in total")
     ap.add_argument("--rhs-evals", type=int, default=100, help="RHS evaluations per reactor in the RHS leg")
     ap.add_argument("--rhs-batches", type=int, default=8, help="distinct state batches cycled in the RHS leg")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 8 per host core)")
@@ -145,31 +148,46 @@ def main():
     info = mech_structure(path)
     fl = algorithmic_flops(info)
 
-    def one_step():
+    tt = torch.zeros(a.reactors, dtype=torch.float64, device=dev)
+    hh = torch.zeros(a.reactors, dtype=torch.float64, device=dev)
+    acc_steps = torch.zeros(a.reactors, dtype=torch.int64, device=dev)
+
+    def one_step(tag):
+        """Integrate the whole batch from its initial state: a loop of bounded launches of the
+        persistent kernel, each resuming every unfinished reactor from its (t, h)."""
         yw.copy_(y0d)
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        r = ck.integrate(g, yw, Pd, ted, method="ros4", workspace=ws, inplace=True, kernel=a.kernel,
-                         precision=a.precision)
-        ev1.record(stream)
-        return r, ev0, ev1
+        tt.zero_()
+        hh.zero_()
+        acc_steps.zero_()
+        launches, kern = 0, 0.0
+        while True:
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            r = ck.integrate(g, yw, Pd, ted, method="ros4", t=tt, h=hh, workspace=ws, inplace=True,
+                             kernel=a.kernel, precision=a.precision, max_steps=a.launch_steps)
+            ev1.record(stream)
+            acc_steps.add_(r["n_accept"] + r["n_reject"])
+            torch.cuda.synchronize()
+            launches += 1
+            kern += ev0.elapsed_time(ev1) / 1e3
+            left = int((r["status"] == 1).sum().item())
+            print(f"{tag} launch {launches}: {ev0.elapsed_time(ev1) / 1e3:.2f} s, {left} reactors unfinished",
+                  file=sys.stderr, flush=True)
+            if left == 0 or launches * a.launch_steps >= a.max_steps:
+                return r, kern, launches
 
     for i in range(a.warmup):
-        r, e0, e1 = one_step()
-        torch.cuda.synchronize()
-        print(f"warmup {i}: {e0.elapsed_time(e1) / 1e3:.2f} s", file=sys.stderr, flush=True)
+        one_step(f"warmup {i}")
     torch.cuda.synchronize()
     kern_s = []
     t0 = time.perf_counter()
     for i in range(a.steps):
-        r, e0, e1 = one_step()
-        torch.cuda.synchronize()
-        kern_s.append(e0.elapsed_time(e1) / 1e3)
-        print(f"step {i}: {kern_s[-1]:.2f} s", file=sys.stderr, flush=True)
+        r, kern, launches = one_step(f"step {i}")
+        kern_s.append(kern)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    steps = (r["n_accept"] + r["n_reject"]).to(torch.float64)
+    steps = acc_steps.to(torch.float64)
     status = torch.bincount(r["status"].to(torch.int64), minlength=4).tolist()
     total_steps = float(steps.sum().item())
     kernel_s = sum(kern_s) / len(kern_s)
@@ -210,12 +228,13 @@ def main():
                    "reactors": a.reactors, "t_end": a.t_end, "kernel": a.kernel, "precision": a.precision},
         "rhs_evals_per_s": rhs_rate,
         "mean_steps_per_reactor": total_steps / a.reactors,
+        "launches_per_step": launches,
         "status_counts": {"ok": status[0], "max_steps": status[1], "h_underflow": status[2], "nonfinite": status[3]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": None,
                      "kernel": "integrate_wave_kernel<Ros4Adapter>" if a.kernel != "lane" else
                      "integrate_lane_kernel<0>",
-                     "flops_per_launch": flops_launch, "kernel_s": kernel_s,
+                     "flops_per_step_of_batch": flops_launch, "kernel_s": kernel_s,
                      "flops_per_step": fl["ros4_step"]},
     }
     if not a.no_cpu_baseline:

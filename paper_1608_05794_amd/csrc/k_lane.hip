@@ -58,39 +58,38 @@ __device__ void rhs_lane(const DevMech &M, const YV &y, double P, SV f, SV w, co
     const double T = y[0];
     const TPow t = tpow(T);
     double S = 0.0;
-    for (int k = 0; k < ns; k++) S += y[1 + k] * M.invW[k];
+    for (int k = 0; k < ns; k++) S += y[1 + k] * M.invW()[k];
     const double rho = P / (M.R * T * S);
     const double Ctot = P * t.invT / M.R;
     double cpm = 0.0;
     for (int k = 0; k < ns; k++) {
-        const double Ck = rho * y[1 + k] * M.invW[k];
+        const double Ck = rho * y[1 + k] * M.invW()[k];
         w[L.C + k] = Ck;
         const Thermo th = species_thermo(M, k, t);
         w[L.G + k] = th.h - th.s;
         w[L.H + k] = th.h;
         w[L.CP + k] = th.cp;
         w[L.WD + k] = 0.0;
-        cpm += y[1 + k] * th.cp * M.invW[k];
+        cpm += y[1 + k] * th.cp * M.invW()[k];
     }
     cpm *= M.R;
     auto Cg = [&](int k) { return w[L.C + k]; };
     auto Gg = [&](int k) { return w[L.G + k]; };
     auto Hg = [&](int k) { return w[L.H + k]; };
     for (int i = 0; i < M.nrxn; i++) {
+        const RxnRec R = M.rx[i];
+        Slots S;
+        const int nmax = rx_nslot(R.meta);
+        load_slots(R, Cg, S, nmax);
         Rate q;
-        reaction_rate<false>(M, i, t, Ctot, Cg, Gg, Hg, q);
+        reaction_rate<false>(M, R, S, nmax, t, Ctot, Cg, Gg, Hg, q);
         const double qi = q.c * (q.kf * q.pf - q.kr * q.pr);
-        const int nsl = M.nslot[i], nre = M.nreac[i];
-        for (int s = 0; s < nsl; s++) {
-            const int sp = M.slot_sp[size_t(s) * M.nrxn + i];
-            const int nu = M.slot_nu[size_t(s) * M.nrxn + i];
-            w[L.WD + sp] += (s < nre ? -nu : nu) * qi;
-        }
+        for (int s = 0; s < S.n; s++) w[L.WD + S.sp[s]] += (S.sgn[s] * S.nu[s]) * qi;
     }
     double Q = 0.0;
     for (int k = 0; k < ns; k++) {
         const double wd = w[L.WD + k];
-        f[1 + k] = M.W[k] * wd / rho;
+        f[1 + k] = M.W()[k] * wd / rho;
         Q += M.R * T * w[L.H + k] * wd;
     }
     f[0] = -Q / (rho * cpm);
@@ -108,7 +107,7 @@ __device__ void jac_lane(const DevMech &M, const YV &y, double P, SV J, SV f, SV
     const TPow t = tpow(T);
     const double Ctot = P * t.invT / M.R;
     double S = 0.0;
-    for (int k = 0; k < ns; k++) S += y[1 + k] * M.invW[k];
+    for (int k = 0; k < ns; k++) S += y[1 + k] * M.invW()[k];
     const double Wbar = 1.0 / S;
     for (int64_t e = 0; e < int64_t(ns) * ns; e++) w[L.JC + e] = 0.0;
     for (int k = 0; k < ns; k++) w[L.DWT + k] = 0.0;
@@ -116,33 +115,32 @@ __device__ void jac_lane(const DevMech &M, const YV &y, double P, SV J, SV f, SV
     auto Gg = [&](int k) { return w[L.G + k]; };
     auto Hg = [&](int k) { return w[L.H + k]; };
     for (int i = 0; i < nr; i++) {
+        const RxnRec R = M.rx[i];
+        Slots S;
+        const int nmax = rx_nslot(R.meta);
+        load_slots(R, Cg, S, nmax);
         Rate q;
-        reaction_rate<true>(M, i, t, Ctot, Cg, Gg, Hg, q);
+        reaction_rate<true>(M, R, S, nmax, t, Ctot, Cg, Gg, Hg, q);
         const double Rn = q.kf * q.pf - q.kr * q.pr;
         const double dqT = q.c * (q.kf * q.dlnkf * q.pf - q.kr * q.dlnkr * q.pr) + Rn * q.dcdT;
-        const int nsl = M.nslot[i], nre = M.nreac[i];
         // mass-action part, slot pairs (row slot a, column slot b)
-        for (int b = 0; b < nsl; b++) {
-            const int spb = M.slot_sp[size_t(b) * nr + i];
-            const double d = dprod_slot(M, i, b, Cg);
-            const double dq = q.c * (b < nre ? q.kf * d : -q.kr * d);
-            for (int a = 0; a < nsl; a++) {
-                const int spa = M.slot_sp[size_t(a) * nr + i];
-                const int nua = M.slot_nu[size_t(a) * nr + i];
-                w[L.JC + int64_t(spa) * ns + spb] += (a < nre ? -nua : nua) * dq;
-            }
+        for (int b = 0; b < S.n; b++) {
+            const double d = dprod_slot(S, b, nmax);
+            const double dq = q.c * (S.sgn[b] < 0 ? q.kf * d : -q.kr * d);
+            for (int a = 0; a < S.n; a++) w[L.JC + int64_t(S.sp[a]) * ns + S.sp[b]] += (S.sgn[a] * S.nu[a]) * dq;
         }
-        for (int a = 0; a < nsl; a++) {
-            const int spa = M.slot_sp[size_t(a) * nr + i];
-            const int nua = M.slot_nu[size_t(a) * nr + i];
-            const double v = (a < nre ? -nua : nua);
-            w[L.DWT + spa] += v * dqT;
+        const int eb = R.eff_begin, ec = rx_neff(R.meta);
+        for (int a = 0; a < S.n; a++) {
+            const double v = S.sgn[a] * S.nu[a];
+            w[L.DWT + S.sp[a]] += v * dqT;
             if (q.dcdM != 0.0) {
                 // d[M]/dC_l = alpha_l = 1 + (alpha_l - 1)
                 const double base = v * Rn * q.dcdM;
-                for (int l = 0; l < ns; l++) w[L.JC + int64_t(spa) * ns + l] += base;
-                const int eb = M.eff_begin[i], ec = M.eff_count[i];
-                for (int e = 0; e < ec; e++) w[L.JC + int64_t(spa) * ns + M.eff_sp[eb + e]] += base * M.eff_am1[eb + e];
+                for (int l = 0; l < ns; l++) w[L.JC + int64_t(S.sp[a]) * ns + l] += base;
+                for (int e = 0; e < ec; e++) {
+                    const EffRec E = M.eff[eb + e];
+                    w[L.JC + int64_t(S.sp[a]) * ns + E.sp] += base * E.am1;
+                }
             }
         }
     }
@@ -151,24 +149,24 @@ __device__ void jac_lane(const DevMech &M, const YV &y, double P, SV J, SV f, SV
     for (int k = 0; k < ns; k++) {
         double jcc = 0.0;
         for (int l = 0; l < ns; l++) jcc += w[L.JC + int64_t(k) * ns + l] * w[L.C + l];
-        const double Wk = M.W[k];
+        const double Wk = M.W()[k];
         const double resid = w[L.WD + k] - jcc;
         const double a = Wk * Wbar * resid / rho;
-        for (int j = 0; j < ns; j++) J[int64_t(1 + k) * N + 1 + j] = M.invW[j] * (Wk * w[L.JC + int64_t(k) * ns + j] + a);
+        for (int j = 0; j < ns; j++) J[int64_t(1 + k) * N + 1 + j] = M.invW()[j] * (Wk * w[L.JC + int64_t(k) * ns + j] + a);
         J[int64_t(1 + k) * N] = (Wk / rho) * (w[L.DWT + k] + resid * t.invT);
         const double Hk = M.R * T * w[L.H + k];
         sumHJCC += Hk * jcc;
         dQT += M.R * w[L.CP + k] * w[L.WD + k] + Hk * (w[L.DWT + k] - jcc * t.invT);
         const Thermo th = species_thermo(M, k, t);
-        sdcp += y[1 + k] * M.R * th.dcp * M.invW[k];
+        sdcp += y[1 + k] * M.R * th.dcp * M.invW()[k];
     }
     const double D = rho * cp;
     const double fT = f[0];
     for (int j = 0; j < ns; j++) {
         double colH = 0.0;
         for (int k = 0; k < ns; k++) colH += M.R * T * w[L.H + k] * w[L.JC + int64_t(k) * ns + j];
-        const double dQ = M.invW[j] * (rho * colH - Wbar * sumHJCC);
-        const double dD = rho * M.invW[j] * (M.R * w[L.CP + j] - cp * Wbar);
+        const double dQ = M.invW()[j] * (rho * colH - Wbar * sumHJCC);
+        const double dD = rho * M.invW()[j] * (M.R * w[L.CP + j] - cp * Wbar);
         J[1 + j] = -(dQ + fT * dD) / D;
     }
     const double dDT = -rho * cp * t.invT + rho * sdcp;

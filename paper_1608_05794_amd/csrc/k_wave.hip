@@ -17,11 +17,19 @@
 
 extern "C" __device__ unsigned long long __ockl_wfred_max_u64(unsigned long long);
 extern "C" __device__ double __ockl_wfred_add_f64(double);
+extern "C" __device__ unsigned int __ockl_wfred_max_u32(unsigned int);
 
 namespace ck {
 namespace {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+// Value the compiler cannot see through: keeps cheap per-phase values (lane masks, pivot
+// lanes) from being hoisted across phases, where they would only occupy and spill SGPRs.
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ int lane_fresh() { return opaque(__lane_id()); }
 __device__ __forceinline__ double wsum(double v) { return __ockl_wfred_add_f64(v); }
 __device__ __forceinline__ double bcast(double v, int src) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -32,17 +40,17 @@ __device__ __forceinline__ bool wave_all(bool v) { return __ballot(!v) == 0ull; 
 
 // ---------------------------------------------------------------------------------------
 // LDS layout of one wavefront (doubles):
-//   C[ns+1] G[ns] H[ns] WD[ns] | IW[64] (1/W_j padded with zeros) |
+//   C[ns+1] G[ns] H[ns] WD[ns] | IW[64] (1/W_j padded with zeros) | VX[64] (broadcast scratch) |
 //   JC[ns*ldj + 64] TB[ns] DWT[ns] TROW[ns + 64]   (Jacobian kernels only)
 // ---------------------------------------------------------------------------------------
 struct Lds {
-    double *C, *G, *H, *WD, *IW, *JC, *TB, *DWT, *TROW;
+    double *C, *G, *H, *WD, *IW, *VX, *JC, *TB, *DWT, *TROW;
     int ldj;
 };
 
 __host__ __device__ inline int ldj_of(int ns) { return ns | 1; }
 __host__ __device__ inline size_t lds_doubles(int ns, bool jac) {
-    size_t d = size_t(ns + 1) + 3 * size_t(ns) + 64;
+    size_t d = size_t(ns + 1) + 3 * size_t(ns) + 128;
     if (jac) d += size_t(ns) * ldj_of(ns) + 64 + 2 * size_t(ns) + size_t(ns) + 64;
     return d;
 }
@@ -55,6 +63,7 @@ __device__ Lds carve(double *b, int ns, bool jac) {
     L.H = b; b += ns;
     L.WD = b; b += ns;
     L.IW = b; b += 64;
+    L.VX = b; b += 64;
     if (jac) {
         L.JC = b; b += size_t(ns) * L.ldj + 64;
         L.TB = b; b += ns;
@@ -68,7 +77,7 @@ __device__ Lds carve(double *b, int ns, bool jac) {
 
 __device__ void init_lds(const DevMech &M, const Lds &L) {
     const int l = lane_id();
-    L.IW[l] = l < M.nsp ? M.invW[l] : 0.0;
+    L.IW[l] = l < M.nsp ? M.invW()[l] : 0.0;
     L.C[M.nsp] = 1.0;
     if (L.TROW) {
         for (int e = l; e < M.nsp + 64; e += 64) L.TROW[e] = 0.0;
@@ -85,8 +94,8 @@ struct Mix {
 };
 
 // Species index held by register slot c of this lane, or -1 (slot 0 of lane 0 is T).
-__device__ __forceinline__ int slot_species(int c, int ns) {
-    const int i = lane_id() + 64 * c;
+__device__ __forceinline__ int slot_species(int c, int ns, int lane) {
+    const int i = lane + 64 * c;
     return (i >= 1 && i <= ns) ? i - 1 : -1;
 }
 
@@ -94,13 +103,14 @@ __device__ __forceinline__ int slot_species(int c, int ns) {
 template <int RPL, bool JAC>
 __device__ void species_pass(const DevMech &M, const double (&y)[RPL], double P, const Lds &L, Mix<RPL> &x) {
     const int ns = M.nsp;
+    const int lane = lane_fresh();
     const double T = bcast(y[0], 0);
     x.t = tpow(T);
     double sy = 0.0;
 #pragma unroll
     for (int c = 0; c < RPL; c++) {
-        const int k = slot_species(c, ns);
-        if (k >= 0) sy += y[c] * M.invW[k];
+        const int k = slot_species(c, ns, lane);
+        if (k >= 0) sy += y[c] * M.invW()[k];
     }
     const double S = wsum(sy);
     x.rho = P / (M.R * T * S);
@@ -109,9 +119,9 @@ __device__ void species_pass(const DevMech &M, const double (&y)[RPL], double P,
     double cpp = 0.0;
 #pragma unroll
     for (int c = 0; c < RPL; c++) {
-        const int k = slot_species(c, ns);
+        const int k = slot_species(c, ns, lane);
         if (k >= 0) {
-            L.C[k] = x.rho * y[c] * M.invW[k];
+            L.C[k] = x.rho * y[c] * M.invW()[k];
             const Thermo th = species_thermo(M, k, x.t);
             L.G[k] = th.h - th.s;
             L.H[k] = th.h;
@@ -119,14 +129,14 @@ __device__ void species_pass(const DevMech &M, const double (&y)[RPL], double P,
             x.cp[c] = th.cp;
             x.h[c] = th.h;
             x.dcp[c] = th.dcp;
-            cpp += y[c] * th.cp * M.invW[k];
+            cpp += y[c] * th.cp * M.invW()[k];
         } else {
             x.cp[c] = x.h[c] = x.dcp[c] = 0.0;
         }
     }
     x.cpm = wsum(cpp) * M.R;
     if (JAC) {
-        const int l = lane_id();
+        const int l = lane;
         const int tot = ns * L.ldj;
         for (int e = l; e < tot; e += 64) L.JC[e] = 0.0;
         for (int e = l; e < ns; e += 64) {
@@ -146,39 +156,48 @@ __device__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, dou
     auto Cg = [&](int k) { return L.C[k]; };
     auto Gg = [&](int k) { return L.G[k]; };
     auto Hg = [&](int k) { return L.H[k]; };
-    for (int i = lane_id(); i < nr; i += 64) {
+    for (int i = lane_fresh(); i < nr; i += 64) {
+        const RxnRec R = M.rx[i];
+        const int nmax = __builtin_amdgcn_readfirstlane(R.blk_slots);
+        Slots S;
+        load_slots(R, Cg, S, nmax);
         Rate q;
-        reaction_rate<JAC>(M, i, t, Ctot, Cg, Gg, Hg, q);
+        reaction_rate<JAC>(M, R, S, nmax, t, Ctot, Cg, Gg, Hg, q);
         const double Rn = q.kf * q.pf - q.kr * q.pr;
         const double qi = q.c * Rn;
-        const int nsl = M.nslot[i], nre = M.nreac[i];
-        for (int s = 0; s < nsl; s++) {
-            const int sp = M.slot_sp[size_t(s) * nr + i];
-            const int nu = M.slot_nu[size_t(s) * nr + i];
-            atomicAdd(&L.WD[sp], (s < nre ? -nu : nu) * qi);
+#pragma unroll
+        for (int s = 0; s < kMaxSlots; s++) {
+            if (s >= nmax) break;
+            if (S.sgn[s] != 0) atomicAdd(&L.WD[S.sp[s]], (S.sgn[s] * S.nu[s]) * qi);
         }
         if (JAC) {
             const double dqT = q.c * (q.kf * q.dlnkf * q.pf - q.kr * q.dlnkr * q.pr) + Rn * q.dcdT;
-            for (int b = 0; b < nsl; b++) {
-                const int spb = M.slot_sp[size_t(b) * nr + i];
-                const double d = dprod_slot(M, i, b, Cg);
-                const double dq = q.c * (b < nre ? q.kf * d : -q.kr * d);
-                for (int a = 0; a < nsl; a++) {
-                    const int spa = M.slot_sp[size_t(a) * nr + i];
-                    const int nua = M.slot_nu[size_t(a) * nr + i];
-                    atomicAdd(&L.JC[spa * L.ldj + spb], (a < nre ? -nua : nua) * dq);
+#pragma unroll
+            for (int b = 0; b < kMaxSlots; b++) {
+                if (b >= nmax) break;
+                if (S.sgn[b] == 0) continue;
+                const double d = dprod_slot(S, b, nmax);
+                const double dq = q.c * (S.sgn[b] < 0 ? q.kf * d : -q.kr * d);
+#pragma unroll
+                for (int a = 0; a < kMaxSlots; a++) {
+                    if (a >= nmax) break;
+                    if (S.sgn[a] != 0) atomicAdd(&L.JC[S.sp[a] * L.ldj + S.sp[b]], (S.sgn[a] * S.nu[a]) * dq);
                 }
             }
-            const int eb = M.eff_begin[i], ec = M.eff_count[i];
-            for (int a = 0; a < nsl; a++) {
-                const int spa = M.slot_sp[size_t(a) * nr + i];
-                const int nua = M.slot_nu[size_t(a) * nr + i];
-                const double v = (a < nre ? -nua : nua);
-                atomicAdd(&L.DWT[spa], v * dqT);
+            const int eb = R.eff_begin, ec = rx_neff(R.meta);
+#pragma unroll
+            for (int a = 0; a < kMaxSlots; a++) {
+                if (a >= nmax) break;
+                if (S.sgn[a] == 0) continue;
+                const double v = S.sgn[a] * S.nu[a];
+                atomicAdd(&L.DWT[S.sp[a]], v * dqT);
                 if (q.dcdM != 0.0) {
                     const double base = v * Rn * q.dcdM;
-                    atomicAdd(&L.TB[spa], base);
-                    for (int e = 0; e < ec; e++) atomicAdd(&L.JC[spa * L.ldj + M.eff_sp[eb + e]], base * M.eff_am1[eb + e]);
+                    atomicAdd(&L.TB[S.sp[a]], base);
+                    for (int e = 0; e < ec; e++) {
+                        const EffRec E = M.eff[eb + e];
+                        atomicAdd(&L.JC[S.sp[a] * L.ldj + E.sp], base * E.am1);
+                    }
                 }
             }
         }
@@ -190,20 +209,21 @@ __device__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, dou
 template <int RPL>
 __device__ void finish_rhs(const DevMech &M, const Lds &L, const Mix<RPL> &x, double (&f)[RPL]) {
     const int ns = M.nsp;
+    const int lane = lane_fresh();
     double qp = 0.0;
 #pragma unroll
     for (int c = 0; c < RPL; c++) {
-        const int k = slot_species(c, ns);
+        const int k = slot_species(c, ns, lane);
         if (k >= 0) {
             const double wd = L.WD[k];
-            f[c] = M.W[k] * wd / x.rho;
+            f[c] = M.W()[k] * wd / x.rho;
             qp += M.R * x.t.T * x.h[c] * wd;
         } else {
             f[c] = 0.0;
         }
     }
     const double Q = wsum(qp);
-    if (lane_id() == 0) f[0] = -Q / (x.rho * x.cpm);
+    if (lane == 0) f[0] = -Q / (x.rho * x.cpm);
 }
 
 template <int RPL>
@@ -223,8 +243,8 @@ struct JRow {
 
 // Chain rule from (d wdot/dC, d wdot/dT) to J = df/dy (N <= 64, one row per lane).
 __device__ JRow jac_prepare(const DevMech &M, const Lds &L, const Mix<1> &x, double y0, double fT) {
-    const int ns = M.nsp, lane = lane_id();
-    const int k = slot_species(0, ns);
+    const int ns = M.nsp, lane = lane_fresh();
+    const int k = slot_species(0, ns, lane);
     const bool valid = k >= 0;
     const double T = x.t.T, RT = M.R * T;
     double jcc = 0.0, colH = 0.0, resid = 0.0, a = 0.0, col0 = 0.0, TBk = 0.0, WDk = 0.0, DWTk = 0.0;
@@ -240,19 +260,19 @@ __device__ JRow jac_prepare(const DevMech &M, const Lds &L, const Mix<1> &x, dou
         jcc += TBk * x.Ctot;
         colH *= RT;
         resid = WDk - jcc;
-        a = M.W[k] * x.Wbar * resid / x.rho;
-        col0 = (M.W[k] / x.rho) * (DWTk + resid * x.t.invT);
+        a = M.W()[k] * x.Wbar * resid / x.rho;
+        col0 = (M.W()[k] / x.rho) * (DWTk + resid * x.t.invT);
     }
     const double Hk = RT * x.h[0];
     const double sumHTB = wsum(valid ? Hk * TBk : 0.0);
     const double sumHJCC = wsum(valid ? Hk * jcc : 0.0);
     const double dQT = wsum(valid ? M.R * x.cp[0] * WDk + Hk * (DWTk - jcc * x.t.invT) : 0.0);
-    const double sdcp = wsum(valid ? y0 * M.R * x.dcp[0] * M.invW[k] : 0.0);
+    const double sdcp = wsum(valid ? y0 * M.R * x.dcp[0] * M.invW()[k] : 0.0);
     const double D = x.rho * x.cpm;
     if (valid) {
-        const double dQ = M.invW[k] * (x.rho * (colH + sumHTB) - x.Wbar * sumHJCC);
-        const double dD = x.rho * M.invW[k] * (M.R * x.cp[0] - x.cpm * x.Wbar);
-        L.TROW[k] = -(dQ + fT * dD) / D * M.W[k];
+        const double dQ = M.invW()[k] * (x.rho * (colH + sumHTB) - x.Wbar * sumHJCC);
+        const double dD = x.rho * M.invW()[k] * (M.R * x.cp[0] - x.cpm * x.Wbar);
+        L.TROW[k] = -(dQ + fT * dD) / D * M.W()[k];
     }
     const double J00 = -(dQT + fT * (-x.rho * x.cpm * x.t.invT + x.rho * sdcp)) / D;
     __syncthreads();
@@ -264,8 +284,8 @@ __device__ JRow jac_prepare(const DevMech &M, const Lds &L, const Mix<1> &x, dou
         r.c0 = J00;
     } else if (valid) {
         r.src = &L.JC[k * L.ldj];
-        r.alpha = M.W[k];
-        r.beta = M.W[k] * TBk + a;
+        r.alpha = M.W()[k];
+        r.beta = M.W()[k] * TBk + a;
         r.c0 = col0;
     } else {
         r.src = L.TROW;
@@ -276,9 +296,12 @@ __device__ JRow jac_prepare(const DevMech &M, const Lds &L, const Mix<1> &x, dou
     return r;
 }
 
-// f(y) and the Jacobian rows (registers) for N <= NP <= 64.
-template <int NP>
-__device__ void jac_rows(const DevMech &M, const Lds &L, double y, double P, double (&a)[NP], double &f) {
+// f(y) and this lane's row of the iteration matrix M = dg I - J (registers, element type T) for
+// N <= NP <= 64.  The row descriptor jr stays valid (with the Jacobian pieces in LDS) until the
+// next Jacobian, so J x products can be formed later without a stored FP64 matrix.
+template <int NP, class T>
+__device__ void jac_rows(const DevMech &M, const Lds &L, double y, double P, double dg, T (&a)[NP], double &f,
+                         JRow &jr) {
     Mix<1> x;
     const double yy[1] = {y};
     double ff[1];
@@ -286,11 +309,28 @@ __device__ void jac_rows(const DevMech &M, const Lds &L, double y, double P, dou
     reaction_pass<true>(M, L, x.t, x.Ctot);
     finish_rhs<1>(M, L, x, ff);
     f = ff[0];
-    const JRow r = jac_prepare(M, L, x, y, bcast(ff[0], 0));
-    a[0] = r.c0;
+    jr = jac_prepare(M, L, x, y, bcast(ff[0], 0));
+    const int lane = lane_fresh();
+    a[0] = T((lane == 0 ? dg : 0.0) - jr.c0);
 #pragma unroll
-    for (int j = 1; j < NP; j++) a[j] = L.IW[j - 1] * (r.alpha * r.src[j - 1] + r.beta);
+    for (int j = 1; j < NP; j++) a[j] = T((lane == j ? dg : 0.0) - L.IW[j - 1] * (jr.alpha * jr.src[j - 1] + jr.beta));
     __syncthreads();
+}
+
+// (J x) for x distributed one component per lane, from the Jacobian pieces in LDS.
+__device__ double jac_times(const DevMech &M, const Lds &L, const JRow &r, double x) {
+    const int lane = lane_fresh();
+    const int ns = M.nsp;
+    const bool sp = lane >= 1 && lane <= ns;
+    const double v = sp ? x * L.IW[lane - 1] : 0.0;      // x_{j+1} / W_j
+    if (sp) L.VX[lane - 1] = v;
+    const double Sv = wsum(v);
+    const double x0 = bcast(x, 0);
+    __syncthreads();
+    double dot = 0.0;
+    for (int j = 0; j < ns; j++) dot += r.src[j] * L.VX[j];
+    __syncthreads();
+    return r.c0 * x0 + r.alpha * dot + r.beta * Sv;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -298,7 +338,7 @@ __device__ void jac_rows(const DevMech &M, const Lds &L, double y, double P, dou
 // ---------------------------------------------------------------------------------------
 template <int NP>
 struct LU {
-    int piv[NP];      // lane holding the pivot row of column k (wave-uniform)
+    int pivv;         // lane k holds the lane of the pivot row of column k
     int ord;          // this lane's pivot order
     double dinv;      // 1 / U[ord][ord]
     bool ok;
@@ -311,12 +351,13 @@ __device__ void lu_factor(double (&a)[NP], LU<NP> &f) {
     f.ord = NP;
     f.dinv = 0.0;
     f.ok = true;
+    f.pivv = 0;
 #pragma unroll
     for (int k = 0; k < NP; k++) {
         const unsigned long long key = done ? 0ull : (unsigned long long)__double_as_longlong(fabs(a[k]));
         const unsigned long long mx = __ockl_wfred_max_u64(key);
         const int p = __builtin_ctzll(__ballot(!done && key == mx));
-        f.piv[k] = p;
+        if (lane == k) f.pivv = p;
         f.ok = f.ok && (mx != 0ull);
         const double inv = 1.0 / bcast(a[k], p);
         if (lane == p) {
@@ -331,21 +372,23 @@ __device__ void lu_factor(double (&a)[NP], LU<NP> &f) {
     }
 }
 
-// Solve (L U) x = P b in place; b and x distributed one component per lane.
+// Solve (L U) x = P b; b and x distributed one component per lane.
 template <int NP>
 __device__ double lu_solve(const double (&a)[NP], const LU<NP> &f, double b) {
-    const int lane = lane_id();
+    const int lane = lane_fresh();
+    const int pivv = opaque(f.pivv);
+    const int ord = opaque(f.ord);
 #pragma unroll
     for (int k = 0; k < NP; k++) {
-        const double yk = bcast(b, f.piv[k]);
-        if (f.ord > k) b = fma(-a[k], yk, b);
+        const double yk = bcast(b, __builtin_amdgcn_readlane(pivv, k));
+        if (ord > k) b = fma(-a[k], yk, b);
     }
     double x = 0.0;
 #pragma unroll
     for (int k = NP - 1; k >= 0; k--) {
-        const double xk = bcast(b * f.dinv, f.piv[k]);
+        const double xk = bcast(b * f.dinv, __builtin_amdgcn_readlane(pivv, k));
         if (lane == k) x = xk;
-        if (f.ord < k) b = fma(-a[k], xk, b);
+        if (ord < k) b = fma(-a[k], xk, b);
     }
     return x;
 }
@@ -358,13 +401,11 @@ struct Ros4Wave {
     static constexpr double qinv = 0.25;
     __device__ static bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
                                 double &e) {
-        const int lane = lane_id();
         double a[NP];
         double f;
-        jac_rows<NP>(M, L, y, P, a, f);
+        JRow jr;
         const double dg = 1.0 / (Ros4::gamma * h);
-#pragma unroll
-        for (int j = 0; j < NP; j++) a[j] = (j == lane) ? dg - a[j] : -a[j];
+        jac_rows<NP, double>(M, L, y, P, dg, a, f, jr);
         LU<NP> lu;
         lu_factor<NP>(a, lu);
         const double ih = 1.0 / h;
@@ -379,6 +420,118 @@ struct Ros4Wave {
         ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
         e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
         return lu.ok;
+    }
+};
+
+// ---------------------------------------------------------------------------------------
+// FP32 factorisation with FP64 residual refinement
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ float bcastf(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double wmax_abs(double v) {
+    return __longlong_as_double((long long)__ockl_wfred_max_u64((unsigned long long)__double_as_longlong(fabs(v))));
+}
+
+template <int NP>
+struct LU32 {
+    int pivv, ord;
+    float dinv;
+    bool ok;
+};
+
+template <int NP>
+__device__ void lu_factor32(float (&a)[NP], LU32<NP> &f) {
+    const int lane = lane_id();
+    bool done = false;
+    f.ord = NP;
+    f.dinv = 0.0f;
+    f.ok = true;
+    f.pivv = 0;
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        const unsigned key = done ? 0u : __float_as_uint(fabsf(a[k]));
+        const unsigned mx = __ockl_wfred_max_u32(key);
+        const int p = __builtin_ctzll(__ballot(!done && key == mx));
+        if (lane == k) f.pivv = p;
+        f.ok = f.ok && (mx != 0u);
+        const float inv = 1.0f / bcastf(a[k], p);
+        if (lane == p) {
+            done = true;
+            f.ord = k;
+            f.dinv = inv;
+        }
+        const float l = done ? 0.0f : a[k] * inv;
+        if (!done) a[k] = l;
+#pragma unroll
+        for (int j = k + 1; j < NP; j++) a[j] = fmaf(-l, bcastf(a[j], p), a[j]);
+    }
+}
+
+template <int NP>
+__device__ float lu_solve32(const float (&a)[NP], const LU32<NP> &f, float b) {
+    const int lane = lane_fresh();
+    const int pivv = opaque(f.pivv);
+    const int ord = opaque(f.ord);
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        const float yk = bcastf(b, __builtin_amdgcn_readlane(pivv, k));
+        if (ord > k) b = fmaf(-a[k], yk, b);
+    }
+    float x = 0.0f;
+#pragma unroll
+    for (int k = NP - 1; k >= 0; k--) {
+        const float xk = bcastf(b * f.dinv, __builtin_amdgcn_readlane(pivv, k));
+        if (lane == k) x = xk;
+        if (ord < k) b = fmaf(-a[k], xk, b);
+    }
+    return x;
+}
+
+// ROS4 step whose linear solves use an FP32 LU of M = I/(gamma h) - J, refined with FP64
+// residuals r = b - M x (M x formed from the FP64 Jacobian pieces).  Refinement stops once the
+// correction is below 2^-48 of the solution; if after the allowed sweeps it is still above
+// 1e-10 of the solution, the step is reported as failed (rejected, so h shrinks and M becomes
+// better conditioned).  With zero sweeps the FP32 solutions are used as they are.
+template <int NP>
+struct Ros4Wave32 {
+    __device__ static bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
+                                double &e, int sweeps) {
+        float a[NP];
+        double f;
+        JRow jr;
+        const double dg = 1.0 / (Ros4::gamma * h);
+        jac_rows<NP, float>(M, L, y, P, dg, a, f, jr);
+        LU32<NP> lu;
+        lu_factor32<NP>(a, lu);
+        bool ok = lu.ok;
+        auto solve = [&](double b) -> double {
+            double x = double(lu_solve32<NP>(a, lu, float(b)));
+            if (sweeps <= 0) return x;
+            double dmax = 0.0, xmax = 0.0;
+            for (int s = 0; s < sweeps; s++) {
+                const double r = b - (dg * x - jac_times(M, L, jr, x));
+                const double d = double(lu_solve32<NP>(a, lu, float(r)));
+                x += d;
+                dmax = wmax_abs(d);
+                xmax = wmax_abs(x);
+                if (dmax <= 0x1p-48 * xmax) break;
+            }
+            if (!(dmax <= 1e-10 * xmax)) ok = false;
+            return x;
+        };
+        const double ih = 1.0 / h;
+        const double u1 = solve(f);
+        double yt[1] = {y + Ros4::a21 * u1}, ft[1];
+        rhs_wave<1>(M, L, yt, P, ft);
+        const double u2 = solve(ft[0] + (Ros4::c21 * u1) * ih);
+        yt[0] = y + Ros4::a31 * u1 + Ros4::a32 * u2;
+        rhs_wave<1>(M, L, yt, P, ft);
+        const double u3 = solve(ft[0] + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
+        const double u4 = solve(ft[0] + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
+        ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
+        e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
+        return ok;
     }
 };
 
@@ -455,8 +608,18 @@ struct Ros4Adapter {
     static constexpr int RPL = 1;
     static constexpr double qinv = 0.25;
     __device__ static bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P, double h,
-                                double (&yn)[1], double (&e)[1]) {
+                                double (&yn)[1], double (&e)[1], const IntOpts &) {
         return Ros4Wave<NP>::step(M, L, y[0], P, h, yn[0], e[0]);
+    }
+};
+
+template <int NP>
+struct Ros4Adapter32 {
+    static constexpr int RPL = 1;
+    static constexpr double qinv = 0.25;
+    __device__ static bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P, double h,
+                                double (&yn)[1], double (&e)[1], const IntOpts &o) {
+        return Ros4Wave32<NP>::step(M, L, y[0], P, h, yn[0], e[0], o.refine_sweeps);
     }
 };
 
@@ -536,7 +699,7 @@ __device__ void integrate_reactor(const DevMech &M, const Lds &L, int64_t r, dou
             const bool clipped = (t + h >= te);
             const double hs = clipped ? te - t : h;
             double yn[RPL], e[RPL];
-            const bool ok = S::step(M, L, yv, P, hs, yn, e);
+            const bool ok = S::step(M, L, yv, P, hs, yn, e, o);
             double err;
             if (o.h_fixed > 0.0)
                 err = 0.0;
@@ -582,7 +745,7 @@ struct Rkf45S {
     static constexpr int RPL = R;
     static constexpr double qinv = 0.2;
     __device__ static bool step(const DevMech &M, const Lds &L, const double (&y)[R], double P, double h,
-                                double (&yn)[R], double (&e)[R]) {
+                                double (&yn)[R], double (&e)[R], const IntOpts &) {
         return Rkf45Wave<R>::step(M, L, y, P, h, yn, e);
     }
 };
@@ -649,7 +812,7 @@ __global__ void __launch_bounds__(64) jac_wave_kernel(DevMech M, int64_t n, cons
 }
 
 template <class S>
-__global__ void __launch_bounds__(64) integrate_wave_kernel(DevMech M, int64_t n, double *y, int64_t ld,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) integrate_wave_kernel(DevMech M, int64_t n, double *y, int64_t ld,
                                                             const double *p, const double *t_end, double *t_io,
                                                             double *h_io, IntOpts o, unsigned *queue,
                                                             int32_t *status, int32_t *nacc, int32_t *nrej, bool jac) {
@@ -694,9 +857,8 @@ int launch_int(const DevMech &M, int64_t n, double *y, int64_t ld, const double 
 }  // namespace
 
 bool wave_supported(const DevMech &M, int method, int precision) {
-    if (precision != CK_PREC_FP64) return false;
     if (method == 0) return M.N <= 64;
-    return M.N <= 128;
+    return precision == CK_PREC_FP64 && M.N <= 128;
 }
 
 size_t wave_ws_bytes(const DevMech &, int64_t) { return 256; }
@@ -728,6 +890,16 @@ int launch_integrate_wave(int method, const DevMech &M, int64_t n, double *y, in
     if (method == 1) {
         if (M.N <= 64) return launch_int<Rkf45S<1>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, false, s);
         return launch_int<Rkf45S<2>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, false, s);
+    }
+    if (o.precision == CK_PREC_FP32_REFINE) {
+        switch (pad_np(M.N)) {
+#define CK_CASE32(NPV) \
+    case NPV: return launch_int<Ros4Adapter32<NPV>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);
+            CK_CASE32(8) CK_CASE32(16) CK_CASE32(24) CK_CASE32(32) CK_CASE32(40) CK_CASE32(48) CK_CASE32(56)
+            CK_CASE32(64)
+#undef CK_CASE32
+            default: return CK_EUNSUPPORTED;
+        }
     }
     switch (pad_np(M.N)) {
         case 8: return launch_int<Ros4Adapter<8>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);

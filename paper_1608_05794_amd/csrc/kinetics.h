@@ -32,8 +32,8 @@ __device__ __forceinline__ TPow tpow(double T) {
 // Species k at temperature t: low range if T < Tmid, else high (per-lane select).
 __device__ __forceinline__ Thermo species_thermo(const DevMech &M, int k, const TPow &t) {
     const int ns = M.nsp;
-    const int off = (t.T < M.Tmid[k]) ? 0 : 21;
-    const double *c = M.thermo + size_t(off) * ns + k;
+    const int off = (t.T < M.Tmid()[k]) ? 0 : 21;
+    const double *c = M.thermo() + size_t(off) * ns + k;
     auto a = [&](int j) { return c[size_t(j) * ns]; };
     Thermo o;
     o.cp = a(0) + a(1) * t.T + a(2) * t.T2 + a(3) * t.T3 + a(4) * t.T4;
@@ -43,12 +43,41 @@ __device__ __forceinline__ Thermo species_thermo(const DevMech &M, int k, const 
     return o;
 }
 
+// x^n for n in 0..3
 __device__ __forceinline__ double ipow(double x, int n) {
-    // n in 1..3 (validated at load)
-    double p = x;
-    if (n >= 2) p *= x;
-    if (n >= 3) p *= x;
-    return p;
+    const double x2 = x * x;
+    return n == 0 ? 1.0 : (n == 1 ? x : (n == 2 ? x2 : x2 * x));
+}
+
+// The species slots of one reaction with their concentrations, in registers.
+struct Slots {
+    double c[kMaxSlots];
+    int sp[kMaxSlots];
+    int nu[kMaxSlots];     // 0 for unused slots
+    int sgn[kMaxSlots];    // -1 reactant, +1 product, 0 unused
+    int n, nre;
+};
+
+// nmax: a wave-uniform bound on the slot count (slots beyond it are skipped by scalar branches).
+template <class Cget>
+__device__ __forceinline__ void load_slots(const RxnRec &R, const Cget &C, Slots &S, int nmax) {
+    S.n = rx_nslot(R.meta);
+    S.nre = rx_nreac(R.meta);
+#pragma unroll
+    for (int s = 0; s < kMaxSlots; s++) {
+        if (s >= nmax) {
+            S.sp[s] = 0;
+            S.nu[s] = 0;
+            S.sgn[s] = 0;
+            S.c[s] = 1.0;
+            continue;
+        }
+        const bool used = s < S.n;
+        S.sp[s] = rx_sp(R, s);
+        S.nu[s] = used ? rx_nu(R, s) : 0;
+        S.sgn[s] = used ? (s < S.nre ? -1 : 1) : 0;
+        S.c[s] = C(used ? S.sp[s] : 0);
+    }
 }
 
 // Everything one reaction contributes at (T, C).
@@ -60,38 +89,35 @@ struct Rate {
     double dcdM, dcdT;    // d c / d[M], d c / dT   (DERIV only)
 };
 
-// Cget(k) returns C_k; Gget(k) returns g_k = H/(RT) - S/R; Hget(k) returns H/(RT).
+// Rate constants and factors of reaction R (Eqs. kfor, krev, kc; third-body and
+// fall-off factor c).  Gget(k) returns g_k = H_k/(RT) - S_k/R, Hget(k) H_k/(RT).
 template <bool DERIV, class Cget, class Gget, class Hget>
-__device__ __forceinline__ void reaction_rate(const DevMech &M, int i, const TPow &t, double Ctot,
-                                              const Cget &C, const Gget &G, const Hget &H, Rate &o) {
-    const int nr = M.nrxn;
-    const double lnkf = M.lnA[i] + M.beta[i] * t.lnT - M.EaR[i] * t.invT;
+__device__ __forceinline__ void reaction_rate(const DevMech &M, const RxnRec &R, const Slots &S, int nmax,
+                                              const TPow &t, double Ctot, const Cget &C, const Gget &G,
+                                              const Hget &H, Rate &o) {
+    const double lnkf = R.lnA + R.beta * t.lnT - R.EaR * t.invT;
     o.kf = exp(lnkf);
-    if (DERIV) o.dlnkf = (M.beta[i] + M.EaR[i] * t.invT) * t.invT;
-    const int ns = M.nslot[i], nre = M.nreac[i];
+    if (DERIV) o.dlnkf = (R.beta + R.EaR * t.invT) * t.invT;
     o.pf = 1.0;
     o.pr = 1.0;
     double sg = 0.0, sh = 0.0;
-    for (int s = 0; s < ns; s++) {
-        const int sp = M.slot_sp[size_t(s) * nr + i];
-        const int nu = M.slot_nu[size_t(s) * nr + i];
-        const double cs = C(sp);
-        const double p = ipow(cs, nu);
-        if (s < nre) {
-            o.pf *= p;
-            sg -= nu * G(sp);
-            if (DERIV) sh -= nu * H(sp);
-        } else {
-            o.pr *= p;
-            sg += nu * G(sp);
-            if (DERIV) sh += nu * H(sp);
-        }
+#pragma unroll
+    for (int s = 0; s < kMaxSlots; s++) {
+        if (s >= nmax) break;
+        const double p = ipow(S.c[s], S.nu[s]);
+        if (S.sgn[s] < 0) o.pf *= p;
+        else o.pr *= p;
+        const int sp = S.sgn[s] != 0 ? S.sp[s] : 0;
+        const double w = double(S.sgn[s] * S.nu[s]);
+        sg += w * G(sp);
+        if (DERIV) sh += w * H(sp);
     }
-    if (M.rev[i]) {
+    const int meta = R.meta;
+    if (rx_rev(meta)) {
         // ln Kc = -sum_j nu_j g_j + dnu ln(p0 / (R T)); kr = kf / Kc
-        const double lnKc = -sg + M.dnu[i] * (M.ln_p0_R - t.lnT);
+        const double lnKc = -sg + R.dnu * (M.ln_p0_R - t.lnT);
         o.kr = exp(lnkf - lnKc);
-        if (DERIV) o.dlnkr = o.dlnkf - (sh - M.dnu[i]) * t.invT;
+        if (DERIV) o.dlnkr = o.dlnkf - (sh - R.dnu) * t.invT;
     } else {
         o.kr = 0.0;
         if (DERIV) o.dlnkr = 0.0;
@@ -101,26 +127,30 @@ __device__ __forceinline__ void reaction_rate(const DevMech &M, int i, const TPo
         o.dcdM = 0.0;
         o.dcdT = 0.0;
     }
-    const int ty = M.type[i];
+    const int ty = rx_type(meta);
     if (ty == kElementary) return;
     double Mc = Ctot;
-    const int eb = M.eff_begin[i], ec = M.eff_count[i];
-    for (int e = 0; e < ec; e++) Mc += M.eff_am1[eb + e] * C(M.eff_sp[eb + e]);
+    const int eb = R.eff_begin, ec = rx_neff(meta);
+    for (int e = 0; e < ec; e++) {
+        const EffRec E = M.eff[eb + e];
+        Mc += E.am1 * C(E.sp);
+    }
     if (ty == kThirdBody) {
         o.c = Mc;
         if (DERIV) o.dcdM = 1.0;
         return;
     }
     // fall-off: Pr = k0 [M] / k_inf, c = Pr / (1 + Pr) F
-    const double lnk0 = M.lnA0[i] + M.beta0[i] * t.lnT - M.Ea0R[i] * t.invT;
+    const FallRec F = M.fall[R.fall];
+    const double lnk0 = F.lnA0 + F.beta0 * t.lnT - F.Ea0R * t.invT;
     const double ratio = exp(lnk0 - lnkf);
     const double Pr = ratio * Mc;
-    double F = 1.0, g = 0.0, dlogF_dL = 0.0, dFc_over_Fc = 0.0;
+    double Fb = 1.0, g = 0.0, dlogF_dL = 0.0, dFc_over_Fc = 0.0;
     if (ty == kTroe) {
-        const double a = M.troe_a[i];
-        const double e3 = exp(-t.T * M.troe_invT3[i]);
-        const double e1 = exp(-t.T * M.troe_invT1[i]);
-        const double e2 = exp(-M.troe_T2[i] * t.invT);
+        const double a = F.a;
+        const double e3 = exp(-t.T * F.invT3);
+        const double e1 = exp(-t.T * F.invT1);
+        const double e2 = exp(-F.T2 * t.invT);
         const double Fc = (1.0 - a) * e3 + a * e1 + e2;
         const double L = log10(fmax(Fc, 1e-300));
         const double cc = -0.4 - 0.67 * L;
@@ -129,43 +159,39 @@ __device__ __forceinline__ void reaction_rate(const DevMech &M, int i, const TPo
         const double d = nn - 0.14 * x;
         const double f1 = x / d;
         const double u = 1.0 + f1 * f1;
-        F = exp10(L / u);
+        Fb = exp10(L / u);
         if (DERIV) {
             const double iu2 = 1.0 / (u * u);
             const double id2 = 1.0 / (d * d);
             g = L * (-2.0 * f1 * iu2) * (nn * id2);
             dlogF_dL = 1.0 / u - L * 2.0 * f1 * iu2 * ((-0.67 * nn + 1.27 * x) * id2);
-            const double dFc = -(1.0 - a) * M.troe_invT3[i] * e3 - a * M.troe_invT1[i] * e1 +
-                               M.troe_T2[i] * t.invT * t.invT * e2;
+            const double dFc = -(1.0 - a) * F.invT3 * e3 - a * F.invT1 * e1 + F.T2 * t.invT * t.invT * e2;
             dFc_over_Fc = dFc / Fc;
         }
     }
     const double onep = 1.0 + Pr;
-    o.c = Pr / onep * F;
+    o.c = Pr / onep * Fb;
     if (DERIV) {
-        const double dc_dPr = F / (onep * onep) + F * g / onep;
-        const double dlnPr_dT = (M.beta0[i] + M.Ea0R[i] * t.invT) * t.invT - o.dlnkf;
+        const double dc_dPr = Fb / (onep * onep) + Fb * g / onep;
+        const double dlnPr_dT = (F.beta0 + F.Ea0R * t.invT) * t.invT - o.dlnkf;
         o.dcdM = dc_dPr * ratio;
         o.dcdT = dc_dPr * Pr * dlnPr_dT;
-        if (ty == kTroe) o.dcdT += Pr / onep * F * dlogF_dL * dFc_over_Fc;
+        if (ty == kTroe) o.dcdT += Pr / onep * Fb * dlogF_dL * dFc_over_Fc;
     }
 }
 
-// d(prod over one side)/dC of slot s (a species may fill one slot per side).
-template <class Cget>
-__device__ __forceinline__ double dprod_slot(const DevMech &M, int i, int s, const Cget &C) {
-    const int nr = M.nrxn;
-    const int nre = M.nreac[i], ns = M.nslot[i];
-    const int lo = s < nre ? 0 : nre, hi = s < nre ? nre : ns;
+// d(prod over the side of slot s)/dC of slot s: nu_s C_s^(nu_s-1) times the side's other factors.
+__device__ __forceinline__ double dprod_slot(const Slots &S, int s, int nmax) {
     double p = 1.0;
-    for (int t = lo; t < hi; t++) {
-        const int sp = M.slot_sp[size_t(t) * nr + i];
-        const int nu = M.slot_nu[size_t(t) * nr + i];
-        const double cs = C(sp);
+#pragma unroll
+    for (int t = 0; t < kMaxSlots; t++) {
+        if (t >= nmax) break;
+        if (S.sgn[t] != S.sgn[s]) continue;
+        const double ct = S.c[t];
         if (t == s)
-            p *= nu == 1 ? 1.0 : (nu == 2 ? 2.0 * cs : 3.0 * cs * cs);
+            p *= S.nu[t] == 1 ? 1.0 : (S.nu[t] == 2 ? 2.0 * ct : 3.0 * ct * ct);
         else
-            p *= ipow(cs, nu);
+            p *= ipow(ct, S.nu[t]);
     }
     return p;
 }

@@ -163,76 +163,87 @@ extern "C" int ck_mechanism_load(const char *path, int device, ck_mech **out) {
     const HostMech &hm = m->host;
     const int ns = hm.nsp, nr = hm.nrxn;
 
-    // species tables
-    std::vector<double> W(ns), invW(ns), Tmid(ns), th(size_t(kThermoCoef) * ns);
+    // species block: W, 1/W, Tmid, then the derived NASA-7 coefficients, each [nsp]
+    std::vector<double> spd(size_t(3 + kThermoCoef) * ns);
     for (int k = 0; k < ns; k++) {
-        W[k] = hm.W[k];
-        invW[k] = 1.0 / hm.W[k];
-        Tmid[k] = hm.Tmid[k];
+        spd[k] = hm.W[k];
+        spd[size_t(ns) + k] = 1.0 / hm.W[k];
+        spd[size_t(2) * ns + k] = hm.Tmid[k];
         for (int rg = 0; rg < 2; rg++) {
             const double *a = rg == 0 ? &hm.alow[7 * k] : &hm.ahigh[7 * k];
             double c[21] = {a[0], a[1], a[2], a[3], a[4],
                             a[0], a[1] / 2.0, a[2] / 3.0, a[3] / 4.0, a[4] / 5.0, a[5],
                             a[0], a[1], a[2] / 2.0, a[3] / 3.0, a[4] / 4.0, a[6],
                             a[1], 2.0 * a[2], 3.0 * a[3], 4.0 * a[4]};
-            for (int j = 0; j < 21; j++) th[size_t(21 * rg + j) * ns + k] = c[j];
+            for (int j = 0; j < 21; j++) spd[size_t(3 + 21 * rg + j) * ns + k] = c[j];
         }
     }
     // reactions sorted by type (stable), so wavefront lanes mostly share a branch
     std::vector<int> order(nr);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hm.rx[a].type < hm.rx[b].type; });
-    std::vector<double> lnA(nr), beta(nr), EaR(nr), dnu(nr), lnA0(nr), beta0(nr), Ea0R(nr);
-    std::vector<double> ta(nr), iT3(nr), iT1(nr), T2(nr);
-    std::vector<int> type(nr), rev(nr), nslot(nr), nreac(nr), sp(size_t(kMaxSlots) * std::max(nr, 1), 0),
-        nu(size_t(kMaxSlots) * std::max(nr, 1), 0), eb(nr), ec(nr), orig(nr), esp;
-    std::vector<double> eam1;
+    std::vector<RxnRec> rx(std::max(nr, 1));
+    std::vector<FallRec> fall;
+    std::vector<EffRec> eff;
+    std::vector<int> orig(std::max(nr, 1));
     for (int ii = 0; ii < nr; ii++) {
         const auto &x = hm.rx[order[ii]];
+        RxnRec &R = rx[ii];
+        std::memset(&R, 0, sizeof(R));
         orig[ii] = order[ii];
-        lnA[ii] = std::log(x.A);
-        beta[ii] = x.beta;
-        EaR[ii] = x.Ea / hm.R;
-        type[ii] = x.type;
-        rev[ii] = x.rev;
-        int s = 0;
+        R.lnA = std::log(x.A);
+        R.beta = x.beta;
+        R.EaR = x.Ea / hm.R;
+        int s = 0, nu = 0, sp[6] = {0, 0, 0, 0, 0, 0};
         double d = 0;
         for (size_t j = 0; j < x.rsp.size(); j++, s++) {
-            sp[size_t(s) * nr + ii] = x.rsp[j];
-            nu[size_t(s) * nr + ii] = x.rnu[j];
+            sp[s] = x.rsp[j];
+            nu |= x.rnu[j] << (2 * s);
             d -= x.rnu[j];
         }
-        nreac[ii] = s;
+        const int nre = s;
         for (size_t j = 0; j < x.psp.size(); j++, s++) {
-            sp[size_t(s) * nr + ii] = x.psp[j];
-            nu[size_t(s) * nr + ii] = x.pnu[j];
+            sp[s] = x.psp[j];
+            nu |= x.pnu[j] << (2 * s);
             d += x.pnu[j];
         }
-        nslot[ii] = s;
-        dnu[ii] = d;
-        lnA0[ii] = x.type >= 2 ? std::log(x.A0) : 0.0;
-        beta0[ii] = x.beta0;
-        Ea0R[ii] = x.Ea0 / hm.R;
-        ta[ii] = x.ta;
-        iT3[ii] = x.type == 3 ? 1.0 / x.T3 : 0.0;
-        iT1[ii] = x.type == 3 ? 1.0 / x.T1 : 0.0;
-        T2[ii] = x.T2;
-        eb[ii] = int(esp.size());
-        for (auto &e : x.eff) {
-            esp.push_back(e.first);
-            eam1.push_back(e.second - 1.0);
+        R.dnu = d;
+        R.meta = (x.type & 3) | ((x.rev ? 1 : 0) << 2) | (s << 3) | (nre << 6) | (int(x.eff.size()) << 9);
+        R.eff_begin = int(eff.size());
+        for (int j = 0; j < 3; j++) R.sp[j] = sp[2 * j] | (sp[2 * j + 1] << 16);
+        R.nu = nu;
+        R.fall = -1;
+        if (x.type >= 2) {
+            FallRec F{};
+            F.lnA0 = std::log(x.A0);
+            F.beta0 = x.beta0;
+            F.Ea0R = x.Ea0 / hm.R;
+            if (x.type == 3) {
+                F.a = x.ta;
+                F.invT3 = 1.0 / x.T3;
+                F.invT1 = 1.0 / x.T1;
+                F.T2 = x.T2;
+            }
+            R.fall = int(fall.size());
+            fall.push_back(F);
         }
-        ec[ii] = int(esp.size()) - eb[ii];
+        for (auto &e : x.eff) {
+            EffRec E{};
+            E.am1 = e.second - 1.0;
+            E.sp = e.first;
+            eff.push_back(E);
+        }
     }
+    for (int b0 = 0; b0 < nr; b0 += 64) {
+        int mx = 0;
+        for (int i = b0; i < std::min(nr, b0 + 64); i++) mx = std::max(mx, rx_nslot(rx[i].meta));
+        for (int i = b0; i < std::min(nr, b0 + 64); i++) rx[i].blk_slots = mx;
+    }
+    if (fall.empty()) fall.resize(1);
+    if (eff.empty()) eff.resize(1);
 
     Packer pk;
-    size_t oW = pk.add(W), oiW = pk.add(invW), oT = pk.add(Tmid), oth = pk.add(th);
-    size_t olnA = pk.add(lnA), obeta = pk.add(beta), oEaR = pk.add(EaR), odnu = pk.add(dnu);
-    size_t otype = pk.add(type), orev = pk.add(rev), onslot = pk.add(nslot), onreac = pk.add(nreac);
-    size_t osp = pk.add(sp), onu = pk.add(nu), oeb = pk.add(eb), oec = pk.add(ec), oesp = pk.add(esp),
-           oeam1 = pk.add(eam1);
-    size_t olnA0 = pk.add(lnA0), obeta0 = pk.add(beta0), oEa0R = pk.add(Ea0R);
-    size_t ota = pk.add(ta), oiT3 = pk.add(iT3), oiT1 = pk.add(iT1), oT2 = pk.add(T2), oorig = pk.add(orig);
+    const size_t ospd = pk.add(spd), orx = pk.add(rx), ofall = pk.add(fall), oeff = pk.add(eff), oorig = pk.add(orig);
 
     m->device = device;
     int prev = 0;
@@ -264,34 +275,13 @@ extern "C" int ck_mechanism_load(const char *path, int device, ck_mech **out) {
     d.nsp = ns;
     d.nrxn = nr;
     d.N = ns + 1;
-    d.n_eff = int(esp.size());
+    d.n_eff = int(eff.size());
     d.R = hm.R;
     d.ln_p0_R = std::log(hm.p0 / hm.R);
-    d.W = reinterpret_cast<const double *>(b + oW);
-    d.invW = reinterpret_cast<const double *>(b + oiW);
-    d.Tmid = reinterpret_cast<const double *>(b + oT);
-    d.thermo = reinterpret_cast<const double *>(b + oth);
-    d.lnA = reinterpret_cast<const double *>(b + olnA);
-    d.beta = reinterpret_cast<const double *>(b + obeta);
-    d.EaR = reinterpret_cast<const double *>(b + oEaR);
-    d.dnu = reinterpret_cast<const double *>(b + odnu);
-    d.type = reinterpret_cast<const int *>(b + otype);
-    d.rev = reinterpret_cast<const int *>(b + orev);
-    d.nslot = reinterpret_cast<const int *>(b + onslot);
-    d.nreac = reinterpret_cast<const int *>(b + onreac);
-    d.slot_sp = reinterpret_cast<const int *>(b + osp);
-    d.slot_nu = reinterpret_cast<const int *>(b + onu);
-    d.eff_begin = reinterpret_cast<const int *>(b + oeb);
-    d.eff_count = reinterpret_cast<const int *>(b + oec);
-    d.eff_sp = reinterpret_cast<const int *>(b + oesp);
-    d.eff_am1 = reinterpret_cast<const double *>(b + oeam1);
-    d.lnA0 = reinterpret_cast<const double *>(b + olnA0);
-    d.beta0 = reinterpret_cast<const double *>(b + obeta0);
-    d.Ea0R = reinterpret_cast<const double *>(b + oEa0R);
-    d.troe_a = reinterpret_cast<const double *>(b + ota);
-    d.troe_invT3 = reinterpret_cast<const double *>(b + oiT3);
-    d.troe_invT1 = reinterpret_cast<const double *>(b + oiT1);
-    d.troe_T2 = reinterpret_cast<const double *>(b + oT2);
+    d.spd = reinterpret_cast<const double *>(b + ospd);
+    d.rx = reinterpret_cast<const RxnRec *>(b + orx);
+    d.fall = reinterpret_cast<const FallRec *>(b + ofall);
+    d.eff = reinterpret_cast<const EffRec *>(b + oeff);
     d.orig_index = reinterpret_cast<const int *>(b + oorig);
     *out = m;
     return CK_OK;

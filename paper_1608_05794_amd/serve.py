@@ -1,0 +1,233 @@
+"""Continuous-batching solve service on one GPU.
+
+Requests (a mechanism, a batch of reactor states, pressures and an end time)
+are admitted into device-resident slot pools, one pool per mechanism, under
+an HBM budget.  The service runs iterations: in each iteration every pool
+with active slots gets one bounded launch of the wavefront work-queue
+integrator (at most `launch_steps` attempted steps per reactor), each pool on
+its own stream so the mechanisms' work overlaps on the device.  Reactors
+resume from their (t, h) in the next iteration, so a request's result does
+not depend on how its work was split into launches or what else was in the
+pool.  A request completes when none of its reactors still has steps left;
+its slots are freed and waiting requests are admitted at the next iteration.
+
+Only the control plane is here (admission, slot bookkeeping, timing); every
+state update runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import ck
+
+ST_MAX_STEPS = 1
+
+
+@dataclass
+class Request:
+    rid: int
+    mech: str
+    y0: np.ndarray            # [N, n] float64
+    P: np.ndarray             # [n] Pa
+    t_end: float
+    arrival: float            # seconds after the stream started
+    admitted: float = -1.0
+    completed: float = -1.0
+    slots: tuple = ()         # (start, stop) in its pool
+    result: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return self.y0.shape[1]
+
+
+class Pool:
+    """Device-resident state of one mechanism: fixed-capacity slot arrays."""
+
+    def __init__(self, mech: ck.Mechanism, capacity: int, method="ros4", launch_steps=500, **opts):
+        dev = mech.device
+        self.mech = mech
+        self.cap = capacity
+        self.method = method
+        self.launch_steps = launch_steps
+        self.opts = opts
+        N = mech.N
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.y = torch.zeros((N, capacity), **f64)
+        self.y[0].fill_(1000.0)
+        self.y[1].fill_(1.0)
+        self.P = torch.full((capacity,), 101325.0, **f64)
+        self.te = torch.zeros(capacity, **f64)       # empty slots: t = t_end = 0, nothing to do
+        self.t = torch.zeros(capacity, **f64)
+        self.h = torch.zeros(capacity, **f64)
+        self.steps = torch.zeros(capacity, dtype=torch.int64, device=dev)
+        self.ws = torch.empty(mech.workspace_bytes(capacity, **opts), dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.Stream(device=dev)          # default priority
+        self.free = [(0, capacity)]                          # sorted free ranges
+        self.active = {}                                     # rid -> Request
+        self.hwm = 0                                         # slots beyond it are empty
+        self.last = None
+
+    # --- slot bookkeeping ----------------------------------------------------------------
+    def bytes_per_reactor(self):
+        return (self.mech.N + 6) * 8 + self.ws.numel() // max(self.cap, 1)
+
+    def alloc(self, n):
+        for i, (a, b) in enumerate(self.free):
+            if b - a >= n:
+                self.free[i] = (a + n, b)
+                if a + n == b:
+                    self.free.pop(i)
+                return a, a + n
+        return None
+
+    def release(self, a, b):
+        self.free.append((a, b))
+        self.free.sort()
+        merged = []
+        for x, y in self.free:
+            if merged and merged[-1][1] == x:
+                merged[-1] = (merged[-1][0], y)
+            else:
+                merged.append((x, y))
+        self.free = merged
+        self.hwm = max((r.slots[1] for r in self.active.values()), default=0)
+
+    def admit(self, req: Request):
+        rng = self.alloc(req.n)
+        if rng is None:
+            return False
+        a, b = rng
+        req.slots = rng
+        with torch.cuda.stream(self.stream):
+            self.y[:, a:b].copy_(torch.as_tensor(req.y0), non_blocking=False)
+            self.P[a:b].copy_(torch.as_tensor(req.P))
+            self.te[a:b].fill_(req.t_end)
+            self.t[a:b].zero_()
+            self.h[a:b].zero_()
+            self.steps[a:b].zero_()
+        self.active[req.rid] = req
+        self.hwm = max(self.hwm, b)
+        return True
+
+    # --- one iteration ---------------------------------------------------------------------
+    def launch(self):
+        if not self.active or self.hwm == 0:
+            self.last = None
+            return
+        n = self.hwm
+        with torch.cuda.stream(self.stream):
+            r = ck.integrate(self.mech, self.y[:, :n], self.P[:n], self.te[:n], method=self.method,
+                             t=self.t[:n], h=self.h[:n], workspace=self.ws, stream=self.stream, inplace=True,
+                             max_steps=self.launch_steps, **self.opts)
+            self.steps[:n].add_(r["n_accept"] + r["n_reject"])
+            self.last = r["status"]
+
+    def harvest(self, now):
+        """Requests whose reactors all finished; frees their slots."""
+        done = []
+        if self.last is None:
+            return done
+        unfinished = (self.last == ST_MAX_STEPS).cpu().numpy()
+        for rid, req in list(self.active.items()):
+            a, b = req.slots
+            if not unfinished[a:b].any():
+                req.completed = now
+                req.result = dict(y=self.y[:, a:b].cpu().numpy(), status=self.last[a:b].cpu().numpy(),
+                                  steps=self.steps[a:b].cpu().numpy())
+                del self.active[rid]
+                self.release(a, b)
+                done.append(req)
+        return done
+
+
+class Server:
+    """Admission by HBM budget and continuous batching over per-mechanism pools."""
+
+    def __init__(self, mechs: dict, capacity: dict, hbm_budget=200e9, launch_steps=500, **opts):
+        self.pools = {k: Pool(m, capacity[k], launch_steps=launch_steps, **opts) for k, m in mechs.items()}
+        self.budget = hbm_budget
+        self.used = 0.0
+        self.waiting = []
+        self.done = []
+        self.iterations = 0
+
+    def _cost(self, req):
+        return req.n * self.pools[req.mech].bytes_per_reactor()
+
+    def run(self, requests, time_limit=None, log=None):
+        """Serve `requests` (sorted by arrival) against the wall clock; returns completed requests."""
+        pending = list(requests)
+        t0 = time.perf_counter()
+        while pending or self.waiting or any(p.active for p in self.pools.values()):
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                self.waiting.append(pending.pop(0))
+            # FIFO admission under the HBM budget and slot capacity
+            while self.waiting:
+                req = self.waiting[0]
+                cost = self._cost(req)
+                if self.used + cost > self.budget or not self.pools[req.mech].admit(req):
+                    break
+                req.admitted = time.perf_counter() - t0
+                self.used += cost
+                self.waiting.pop(0)
+            if not any(p.active for p in self.pools.values()):
+                if pending:
+                    time.sleep(max(0.0, min(pending[0].arrival - now, 0.01)))
+                continue
+            for p in self.pools.values():
+                p.launch()
+            for p in self.pools.values():
+                p.stream.synchronize()
+            self.iterations += 1
+            now = time.perf_counter() - t0
+            for p in self.pools.values():
+                for req in p.harvest(now):
+                    self.used -= self._cost(req)
+                    self.done.append(req)
+            if log and self.iterations % 20 == 0:
+                log(f"iteration {self.iterations}: t={now:.1f}s done {len(self.done)} waiting {len(self.waiting)} "
+                    f"active {sum(len(p.active) for p in self.pools.values())}")
+            if time_limit and now > time_limit:
+                break
+        return self.done
+
+
+def poisson_requests(n_requests, rate, seed=5000, mech_weights=(("M13", 0.3), ("M53", 0.5), ("M111", 0.2)),
+                     n_range=(1, 65536), t_range=(1e-6, 1e-3), species=None):
+    """Seeded request stream: Poisson arrivals, mechanism by weight, log-uniform size and end time.
+
+    species: dict name -> number of species (to draw states); states follow the configurations
+    (13 species: 1 atm 'small'; 53: 'mid'; 111: 'divergent')."""
+    from . import synth
+    rng = np.random.default_rng(seed)
+    names = [m for m, _ in mech_weights]
+    w = np.array([p for _, p in mech_weights], dtype=float)
+    w /= w.sum()
+    recipe = {"M13": "small", "M53": "mid", "M111": "divergent"}
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        m = names[rng.choice(len(names), p=w)]
+        n = int(np.floor(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1] + 1)))))
+        n = max(n_range[0], min(n, n_range[1]))
+        te = float(np.exp(rng.uniform(np.log(t_range[0]), np.log(t_range[1]))))
+        y0, P = synth.reactor_states(species[m], n, recipe[m], seed=int(rng.integers(1 << 31)))
+        out.append(Request(i, m, y0, P, te, t))
+    return out
+
+
+def latency_summary(done, offered_rate, elapsed):
+    lat = np.array([r.completed - r.arrival for r in done]) if done else np.zeros(0)
+    reactors = sum(r.n for r in done)
+    return dict(completed=len(done), offered_rate=offered_rate,
+                served_rate=len(done) / elapsed if elapsed > 0 else 0.0,
+                reactors_per_s=reactors / elapsed if elapsed > 0 else 0.0,
+                p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
+                p99_s=float(np.percentile(lat, 99)) if len(lat) else None)

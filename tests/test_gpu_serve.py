@@ -1,0 +1,55 @@
+"""Continuous batching: every request's result is the same served in a mix as integrated alone."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1608_05794_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_alone_equals_mix(mech_path):
+    from paper_1608_05794_amd import ck, serve
+    mechs = {k: ck.Mechanism(mech_path(k)) for k in ("M13", "M53")}
+    species = {k: m.n_species for k, m in mechs.items()}
+    reqs = serve.poisson_requests(12, rate=200.0, seed=77, mech_weights=(("M13", 0.5), ("M53", 0.5)),
+                                  n_range=(1, 300), t_range=(1e-9, 2e-8), species=species)
+    srv = serve.Server(mechs, capacity={"M13": 2048, "M53": 2048}, hbm_budget=1e9, launch_steps=37)
+    done = srv.run(reqs, time_limit=300)
+    assert len(done) == len(reqs)
+    assert srv.iterations > 1
+    for r in done:
+        g = mechs[r.mech]
+        alone = ck.integrate(g, torch.as_tensor(r.y0, device="cuda"), torch.as_tensor(r.P, device="cuda"),
+                             r.t_end, method="ros4")
+        torch.cuda.synchronize()
+        assert np.array_equal(alone["status"].cpu().numpy(), r.result["status"])
+        assert np.array_equal(alone["y"].cpu().numpy(), r.result["y"]), r.rid
+        assert np.array_equal((alone["n_accept"] + alone["n_reject"]).cpu().numpy(), r.result["steps"])
+        assert r.completed >= r.admitted >= r.arrival - 1e-9
+    s = serve.latency_summary(done, 200.0, max(r.completed for r in done))
+    print(f"[serve] {s}", flush=True)
+    assert s["p50_s"] <= s["p99_s"]
+
+
+def test_admission_respects_budget(mech_path):
+    from paper_1608_05794_amd import ck, serve
+    mechs = {"M13": ck.Mechanism(mech_path("M13"))}
+    reqs = serve.poisson_requests(6, rate=1e6, seed=78, mech_weights=(("M13", 1.0),), n_range=(200, 200),
+                                  t_range=(1e-9, 1e-9), species={"M13": 13})
+    pool_bytes = 200 * serve.Pool(mechs["M13"], 1024).bytes_per_reactor()
+    # room for exactly two requests at a time
+    srv = serve.Server(mechs, capacity={"M13": 1024}, hbm_budget=2.5 * pool_bytes, launch_steps=10)
+    peak = []
+    orig = serve.Pool.admit
+
+    def spy(self, req):
+        ok = orig(self, req)
+        peak.append(len(self.active))
+        return ok
+    serve.Pool.admit = spy
+    try:
+        done = srv.run(reqs, time_limit=120)
+    finally:
+        serve.Pool.admit = orig
+    assert len(done) == 6 and max(peak) <= 2
