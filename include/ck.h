@@ -52,9 +52,11 @@ enum {
 
 /* Kernel choice for the integrators. */
 enum {
-    CK_KERNEL_AUTO = 0,    /* wavefront-per-reactor work queue where supported, else lane-per-reactor */
+    CK_KERNEL_AUTO = 0,    /* ROS4: WAVE if N <= 64, else GROUP if N <= 128; RKF45: WAVE if N <= 128 */
     CK_KERNEL_LANE = 1,    /* one reactor per lane, all scratch in global memory (Algorithm 2 analogue) */
-    CK_KERNEL_WAVE = 2     /* one reactor per 64-lane wavefront, persistent work queue */
+    CK_KERNEL_WAVE = 2,    /* one reactor per 64-lane wavefront, persistent work queue, LU in registers */
+    CK_KERNEL_GROUP = 3    /* ROS4 only: one reactor per workgroup of 1 (N <= 64) or 2 (N <= 128)
+                              wavefronts, persistent work queue, Gauss-Jordan inverse in registers */
 };
 
 /* Precision of the Rosenbrock linear solves. */

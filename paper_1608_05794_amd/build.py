@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libck.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["mech.hip", "k_lane.hip", "k_wave.hip", "api.hip"]
+SOURCES = ["mech.hip", "k_lane.hip", "k_wave.hip", "k_coop.hip", "api.hip"]
 ARCH = os.environ.get("CK_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libck.so")
 
-KERNELS = {"auto": 0, "lane": 1, "wave": 2}
+KERNELS = {"auto": 0, "lane": 1, "wave": 2, "group": 3}
 PRECISIONS = {"fp64": 0, "fp32_refine": 1}
 STATUS = {0: "ok", 1: "max_steps", 2: "h_underflow", 3: "nonfinite"}
 

@@ -1,6 +1,6 @@
 // C-ABI entry points: argument validation, workspace management and kernel
-// selection.  Every compute step runs in the kernels of k_lane.hip and
-// k_wave.hip.
+// selection.  Every compute step runs in the kernels of k_lane.hip,
+// k_wave.hip and k_coop.hip.
 #include <climits>
 #include <cmath>
 #include <mutex>
@@ -58,7 +58,7 @@ int validate_opts(const ck_opts *o, IntOpts &io) {
     if (!(o->h_fixed >= 0.0) || !(o->h0 >= 0.0)) return CK_EINVAL;
     if (o->h_fixed == 0.0 && !(o->rtol > 0.0)) return CK_EINVAL;
     if (!(o->atol >= 0.0) || o->max_steps < 1) return CK_EINVAL;
-    if (o->kernel < CK_KERNEL_AUTO || o->kernel > CK_KERNEL_WAVE) return CK_EINVAL;
+    if (o->kernel < CK_KERNEL_AUTO || o->kernel > CK_KERNEL_GROUP) return CK_EINVAL;
     if (o->precision != CK_PREC_FP64 && o->precision != CK_PREC_FP32_REFINE) return CK_EINVAL;
     if (o->refine_sweeps < 0 || o->refine_sweeps > 3) return CK_EINVAL;
     io.rtol = o->rtol;
@@ -71,18 +71,23 @@ int validate_opts(const ck_opts *o, IntOpts &io) {
     return CK_OK;
 }
 
-// Kernel family an integrate call will use (CK_KERNEL_LANE or CK_KERNEL_WAVE), or an error.
+// Kernel family an integrate call will use (CK_KERNEL_LANE / WAVE / GROUP), or an error.
 int choose_kernel(const ck_mech *m, int method, const ck_opts *o) {
     ck_opts d;
     ck_opts_default(&d);
     if (!o) o = &d;
+    const bool fp64 = o->precision == CK_PREC_FP64;
     const bool wave_ok = wave_supported(m->dev, method, o->precision);
-    if (o->kernel == CK_KERNEL_WAVE || o->kernel == CK_KERNEL_AUTO) {
-        if (wave_ok) return CK_KERNEL_WAVE;
-        if (o->kernel == CK_KERNEL_WAVE || o->precision != CK_PREC_FP64) return CK_EUNSUPPORTED;
+    const bool group_ok = method == 0 && fp64 && coop_supported(m->dev);
+    switch (o->kernel) {
+        case CK_KERNEL_WAVE: return wave_ok ? CK_KERNEL_WAVE : CK_EUNSUPPORTED;
+        case CK_KERNEL_GROUP: return group_ok ? CK_KERNEL_GROUP : CK_EUNSUPPORTED;
+        case CK_KERNEL_LANE: return fp64 ? CK_KERNEL_LANE : CK_EUNSUPPORTED;
+        default:
+            if (wave_ok) return CK_KERNEL_WAVE;
+            if (group_ok) return CK_KERNEL_GROUP;
+            return fp64 ? CK_KERNEL_LANE : CK_EUNSUPPORTED;
     }
-    if (o->precision != CK_PREC_FP64) return CK_EUNSUPPORTED;
-    return CK_KERNEL_LANE;
 }
 
 size_t lane_bytes(const ck_mech *m, int64_t n, int method) {
@@ -113,6 +118,8 @@ int integrate(int method, const ck_mech *mc, int64_t n, double *y, int64_t ld, c
     }
     if (kern == CK_KERNEL_WAVE)
         return launch_integrate_wave(method, m->dev, n, y, ld, p, t_end, t, h, io, ws, status, nacc, nrej, s);
+    if (kern == CK_KERNEL_GROUP)
+        return launch_integrate_coop(m->dev, n, y, ld, p, t_end, t, h, io, ws, status, nacc, nrej, s);
     const int64_t S = round_up(n, 64);
     return launch_integrate_lane(method, m->dev, n, y, ld, p, t_end, t, h, io, static_cast<double *>(ws), S, status,
                                  nacc, nrej, s);
@@ -197,7 +204,7 @@ extern "C" size_t ck_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts 
         const int k = choose_kernel(m, method, o);
         size_t b = 256;
         if (k == CK_KERNEL_LANE) b = lane_bytes(m, n, method);
-        else if (k == CK_KERNEL_WAVE) b = wave_ws_bytes(m->dev, n);
+        else if (k == CK_KERNEL_WAVE || k == CK_KERNEL_GROUP) b = wave_ws_bytes(m->dev, n);
         if (b > best) best = b;
     }
     return best;

@@ -1,0 +1,580 @@
+// Workgroup-cooperative ROS4: W wavefronts (64 W threads) own one reactor.
+//   - thread t holds state component t (T on thread 0, Y_{t-1} on thread t);
+//   - source term and Jacobian as in the wavefront kernels (species phases
+//     thread-per-species, reaction phases thread-per-reaction with LDS FP64
+//     atomics), with group-wide reductions and broadcasts through LDS when W > 1;
+//   - for W = 2 the Jacobian's d wdot/dC is staged in LDS in two column
+//     windows, so two reactors fit in one CU's LDS;
+//   - the iteration matrix M = I/(gamma h) - J lives in registers, one row per
+//     thread, and is inverted in place by Gauss-Jordan elimination with partial
+//     pivoting.  Each elimination step rotates the row left by one, so the
+//     pivot column is always register 0 and the loop body is the same code for
+//     every step (a runtime loop, small code).  The four stage solves of a
+//     step are then matrix-vector products with no sequential substitution.
+// Reactors come from the same device work queue as the wavefront kernels.
+#include "ck_internal.h"
+#include "kinetics.h"
+#include "launch.h"
+
+extern "C" __device__ unsigned long long __ockl_wfred_max_u64(unsigned long long);
+extern "C" __device__ double __ockl_wfred_add_f64(double);
+
+namespace ck {
+namespace coop {
+
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// LDS layout of one workgroup (doubles); WIN = Jacobian columns staged per window:
+//   C[ns+1] G[ns] H[ns] WD[ns] | IW[128] | VX[128] | RED[16] | PB[2][128] BS[128] XS[128] |
+//   JC[ns * ldj + 128] TB[ns] DWT[ns] TROW[ns + 128]
+struct Lds {
+    double *C, *G, *H, *WD, *IW, *VX, *RED, *PB, *BS, *XS, *JC, *TB, *DWT, *TROW;
+    int ldj;
+};
+
+__host__ __device__ inline int ldj_of(int win) { return win | 1; }
+__host__ __device__ inline size_t lds_doubles(int ns, int win) {
+    return size_t(ns + 1) + 3 * size_t(ns) + 128 + 128 + 16 + 2 * 128 + 128 + 128 + size_t(ns) * ldj_of(win) + 128 +
+           2 * size_t(ns) + size_t(ns) + 128;
+}
+
+__device__ Lds carve(double *b, int ns, int win) {
+    Lds L;
+    L.ldj = ldj_of(win);
+    L.C = b; b += ns + 1;
+    L.G = b; b += ns;
+    L.H = b; b += ns;
+    L.WD = b; b += ns;
+    L.IW = b; b += 128;
+    L.VX = b; b += 128;
+    L.RED = b; b += 16;
+    L.PB = b; b += 2 * 128;
+    L.BS = b; b += 128;
+    L.XS = b; b += 128;
+    L.JC = b; b += size_t(ns) * L.ldj + 128;
+    L.TB = b; b += ns;
+    L.DWT = b; b += ns;
+    L.TROW = b;
+    return L;
+}
+
+// Group primitives for W wavefronts.
+template <int W>
+struct Grp {
+    static constexpr int T = 64 * W;
+    __device__ static int tid() { return opaque(int(threadIdx.x)); }
+    __device__ static int lane() { return int(threadIdx.x) & 63; }
+    __device__ static int wave() { return __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6); }
+    __device__ static double sum(double v, double *red) {
+        const double s = __ockl_wfred_add_f64(v);
+        if (W == 1) return s;
+        if (lane() == 0) red[wave()] = s;
+        __syncthreads();
+        double t = red[0];
+#pragma unroll
+        for (int w = 1; w < W; w++) t += red[w];
+        __syncthreads();
+        return t;
+    }
+    // value of thread src (src uniform)
+    __device__ static double bcast(double v, int src, double *slot) {
+        if (W == 1) return readlane_d(v, src);
+        if (int(threadIdx.x) == src) *slot = v;
+        __syncthreads();
+        const double r = *slot;
+        __syncthreads();
+        return r;
+    }
+    // thread holding the largest key (lowest thread index on ties) and the key itself
+    __device__ static int argmax(unsigned long long key, double *xs, unsigned long long &best) {
+        const unsigned long long mx = __ockl_wfred_max_u64(key);
+        const int l = __builtin_ctzll(__ballot(key == mx));
+        if (W == 1) {
+            best = mx;
+            return l;
+        }
+        unsigned long long *x = reinterpret_cast<unsigned long long *>(xs);
+        if (lane() == 0) {
+            x[2 * wave()] = mx;
+            x[2 * wave() + 1] = (unsigned long long)(wave() * 64 + l);
+        }
+        __syncthreads();
+        best = x[0];
+        int bt = int(x[1]);
+#pragma unroll
+        for (int w = 1; w < W; w++)
+            if (x[2 * w] > best) {
+                best = x[2 * w];
+                bt = int(x[2 * w + 1]);
+            }
+        __syncthreads();
+        return __builtin_amdgcn_readfirstlane(bt);
+    }
+};
+
+__device__ void init_lds(const DevMech &M, const Lds &L, int tid, int nthreads) {
+    for (int e = tid; e < 128; e += nthreads) {
+        L.IW[e] = e < M.nsp ? M.invW()[e] : 0.0;
+        L.VX[e] = 0.0;
+    }
+    for (int e = tid; e < M.nsp + 128; e += nthreads) L.TROW[e] = 0.0;
+    __syncthreads();
+}
+
+struct Mix {
+    TPow t;
+    double rho, Wbar, Ctot, cpm, cp, h, dcp;
+};
+
+__device__ __forceinline__ int species_of(int tid, int ns) { return (tid >= 1 && tid <= ns) ? tid - 1 : -1; }
+
+// Mixture state and species thermodynamics (Section 3); zeroes the accumulators.
+template <int W, bool JAC>
+__device__ void species_pass(const DevMech &M, double y, double P, const Lds &L, Mix &x) {
+    using G = Grp<W>;
+    const int ns = M.nsp, tid = G::tid();
+    const int k = species_of(tid, ns);
+    const double T = G::bcast(y, 0, L.RED + 8);
+    x.t = tpow(T);
+    const double S = G::sum(k >= 0 ? y * M.invW()[k] : 0.0, L.RED);
+    x.rho = P / (M.R * T * S);
+    x.Wbar = 1.0 / S;
+    x.Ctot = P * x.t.invT / M.R;
+    double cpp = 0.0;
+    if (k >= 0) {
+        L.C[k] = x.rho * y * M.invW()[k];
+        const Thermo th = species_thermo(M, k, x.t);
+        L.G[k] = th.h - th.s;
+        L.H[k] = th.h;
+        L.WD[k] = 0.0;
+        x.cp = th.cp;
+        x.h = th.h;
+        x.dcp = th.dcp;
+        cpp = y * th.cp * M.invW()[k];
+    } else {
+        x.cp = x.h = x.dcp = 0.0;
+    }
+    x.cpm = G::sum(cpp, L.RED) * M.R;
+    if (JAC)
+        for (int e = tid; e < ns; e += G::T) {
+            L.TB[e] = 0.0;
+            L.DWT[e] = 0.0;
+        }
+    __syncthreads();
+}
+
+// Rates of progress into WD (FIRST window only) and d wdot/dC for columns [c0, c0 + win) into JC.
+template <int W, bool JAC>
+__device__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, double Ctot, int c0, int win, bool first) {
+    using G = Grp<W>;
+    const int nr = M.nrxn, ns = M.nsp, tid = G::tid();
+    if (JAC) {
+        const int tot = ns * L.ldj;
+        for (int e = tid; e < tot; e += G::T) L.JC[e] = 0.0;
+        __syncthreads();
+    }
+    auto Cg = [&](int k) { return L.C[k]; };
+    auto Gg = [&](int k) { return L.G[k]; };
+    auto Hg = [&](int k) { return L.H[k]; };
+    for (int i = tid; i < nr; i += G::T) {
+        const RxnRec R = M.rx[i];
+        const int nmax = __builtin_amdgcn_readfirstlane(R.blk_slots);
+        Slots S;
+        load_slots(R, Cg, S, nmax);
+        Rate q;
+        reaction_rate<JAC>(M, R, S, nmax, t, Ctot, Cg, Gg, Hg, q);
+        const double Rn = q.kf * q.pf - q.kr * q.pr;
+        if (first) {
+            const double qi = q.c * Rn;
+#pragma unroll
+            for (int s = 0; s < kMaxSlots; s++) {
+                if (s >= nmax) break;
+                if (S.sgn[s] != 0) atomicAdd(&L.WD[S.sp[s]], (S.sgn[s] * S.nu[s]) * qi);
+            }
+        }
+        if (JAC) {
+#pragma unroll
+            for (int b = 0; b < kMaxSlots; b++) {
+                if (b >= nmax) break;
+                const int col = S.sp[b] - c0;
+                if (S.sgn[b] == 0 || col < 0 || col >= win) continue;
+                const double d = dprod_slot(S, b, nmax);
+                const double dq = q.c * (S.sgn[b] < 0 ? q.kf * d : -q.kr * d);
+#pragma unroll
+                for (int a = 0; a < kMaxSlots; a++) {
+                    if (a >= nmax) break;
+                    if (S.sgn[a] != 0) atomicAdd(&L.JC[S.sp[a] * L.ldj + col], (S.sgn[a] * S.nu[a]) * dq);
+                }
+            }
+            const int eb = R.eff_begin, ec = rx_neff(R.meta);
+            const double dqT = q.c * (q.kf * q.dlnkf * q.pf - q.kr * q.dlnkr * q.pr) + Rn * q.dcdT;
+#pragma unroll
+            for (int a = 0; a < kMaxSlots; a++) {
+                if (a >= nmax) break;
+                if (S.sgn[a] == 0) continue;
+                const double v = S.sgn[a] * S.nu[a];
+                if (first) atomicAdd(&L.DWT[S.sp[a]], v * dqT);
+                if (q.dcdM != 0.0) {
+                    const double base = v * Rn * q.dcdM;
+                    if (first) atomicAdd(&L.TB[S.sp[a]], base);
+                    for (int e = 0; e < ec; e++) {
+                        const EffRec E = M.eff[eb + e];
+                        const int col = E.sp - c0;
+                        if (col >= 0 && col < win) atomicAdd(&L.JC[S.sp[a] * L.ldj + col], base * E.am1);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Eqs. ydot and tdot.
+template <int W>
+__device__ double finish_rhs(const DevMech &M, const Lds &L, const Mix &x) {
+    using G = Grp<W>;
+    const int tid = G::tid();
+    const int k = species_of(tid, M.nsp);
+    double f = 0.0, qp = 0.0;
+    if (k >= 0) {
+        const double wd = L.WD[k];
+        f = M.W()[k] * wd / x.rho;
+        qp = M.R * x.t.T * x.h * wd;
+    }
+    const double Q = G::sum(qp, L.RED);
+    if (tid == 0) f = -Q / (x.rho * x.cpm);
+    return f;
+}
+
+template <int W>
+__device__ double rhs(const DevMech &M, const Lds &L, double y, double P) {
+    Mix x;
+    species_pass<W, false>(M, y, P, L, x);
+    reaction_pass<W, false>(M, L, x.t, x.Ctot, 0, 0, true);
+    const double f = finish_rhs<W>(M, L, x);
+    __syncthreads();
+    return f;
+}
+
+// f(y) and this thread's row of M = dg I - J in registers (NP columns), d wdot/dC staged in NWIN
+// column windows of width WIN.
+template <int W, int NP, int NWIN, int WIN>
+__device__ void iteration_rows(const DevMech &M, const Lds &L, double y, double P, double dg, double (&a)[NP],
+                               double &f) {
+    using G = Grp<W>;
+    const int ns = M.nsp;
+    Mix x;
+    species_pass<W, true>(M, y, P, L, x);
+    const int tid = G::tid();
+    const int k = species_of(tid, ns);
+    const bool valid = k >= 0;
+    double jcc = 0.0, colH = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; j++) a[j] = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWIN; w++) {
+        const int c0 = w * WIN;
+        reaction_pass<W, true>(M, L, x.t, x.Ctot, c0, WIN, w == 0);
+        if (w == 0) f = finish_rhs<W>(M, L, x);
+        if (valid) {
+            const double *row = &L.JC[k * L.ldj];
+#pragma unroll
+            for (int j = 0; j < WIN; j++) {
+                if (c0 + j >= ns) break;
+                const double v = row[j];
+                a[1 + c0 + j] = v;                   // raw d wdot_k / dC_(c0+j) for now
+                jcc += v * L.C[c0 + j];
+            }
+            if (k >= c0 && k < c0 + WIN)
+                for (int r = 0; r < ns; r++) colH += L.H[r] * L.JC[r * L.ldj + (k - c0)];
+        }
+        __syncthreads();
+    }
+    // chain rule (as in the wavefront kernels)
+    const double T = x.t.T, RT = M.R * T;
+    double resid = 0.0, ra = 0.0, col0 = 0.0, TBk = 0.0, WDk = 0.0, DWTk = 0.0;
+    if (valid) {
+        TBk = L.TB[k];
+        WDk = L.WD[k];
+        DWTk = L.DWT[k];
+        jcc += TBk * x.Ctot;
+        colH *= RT;
+        resid = WDk - jcc;
+        ra = M.W()[k] * x.Wbar * resid / x.rho;
+        col0 = (M.W()[k] / x.rho) * (DWTk + resid * x.t.invT);
+    }
+    const double Hk = RT * x.h;
+    const double sumHTB = G::sum(valid ? Hk * TBk : 0.0, L.RED);
+    const double sumHJCC = G::sum(valid ? Hk * jcc : 0.0, L.RED);
+    const double dQT = G::sum(valid ? M.R * x.cp * WDk + Hk * (DWTk - jcc * x.t.invT) : 0.0, L.RED);
+    const double sdcp = G::sum(valid ? y * M.R * x.dcp * M.invW()[k] : 0.0, L.RED);
+    const double fT = G::bcast(f, 0, L.RED + 8);
+    const double D = x.rho * x.cpm;
+    if (valid) {
+        const double dQ = M.invW()[k] * (x.rho * (colH + sumHTB) - x.Wbar * sumHJCC);
+        const double dD = x.rho * M.invW()[k] * (M.R * x.cp - x.cpm * x.Wbar);
+        L.TROW[k] = -(dQ + fT * dD) / D;
+    }
+    const double J00 = -(dQT + fT * (-x.rho * x.cpm * x.t.invT + x.rho * sdcp)) / D;
+    __syncthreads();
+    const double alpha = valid ? M.W()[k] : 0.0;
+    const double beta = valid ? M.W()[k] * TBk + ra : 0.0;
+    a[0] = (tid == 0 ? dg : 0.0) - (tid == 0 ? J00 : col0);
+#pragma unroll
+    for (int j = 1; j < NP; j++) {
+        const double Jv = tid == 0 ? L.TROW[j - 1] : L.IW[j - 1] * (alpha * a[j] + beta);
+        a[j] = (tid == j ? dg : 0.0) - Jv;
+    }
+    __syncthreads();
+}
+
+// In-place Gauss-Jordan inverse with partial pivoting and row rotation.  On return the thread
+// whose pivot order is k holds row k of M^-1 with columns permuted: a[j] = Minv[k][p_j], p_j the
+// thread that was pivot j.  Threads with index >= NP hold no row.
+template <int W, int NP>
+__device__ bool gj_invert(double (&a)[NP], const Lds &L, int &ord) {
+    using G = Grp<W>;
+    const int tid = G::tid();
+    bool done = tid >= NP;
+    bool ok = true;
+    ord = NP;
+    for (int k = 0; k < NP; k++) {
+        const double f = a[0];
+        const unsigned long long key = done ? 0ull : (unsigned long long)__double_as_longlong(fabs(f));
+        unsigned long long best;
+        const int p = G::argmax(key, L.RED, best);
+        ok = ok && best != 0ull;
+        double *buf = L.PB + (k & 1) * 128;
+        if (tid == p) {
+            const double r = 1.0 / f;
+#pragma unroll
+            for (int j = 0; j < NP - 1; j++) a[j] = a[j + 1] * r;
+            a[NP - 1] = r;
+#pragma unroll
+            for (int j = 0; j < NP; j++) buf[j] = a[j];
+            done = true;
+            ord = k;
+        }
+        __syncthreads();
+        if (tid != p) {
+#pragma unroll
+            for (int j = 0; j < NP - 1; j++) a[j] = fma(-f, buf[j], a[j + 1]);
+            a[NP - 1] = -f * buf[NP - 1];
+        }
+    }
+    __syncthreads();
+    return ok;
+}
+
+// x = M^-1 b with the rotated inverse; b and x one component per thread.
+template <int W, int NP>
+__device__ double gj_apply(const double (&a)[NP], const Lds &L, int ord, double b) {
+    using G = Grp<W>;
+    const int tid = G::tid();
+    if (ord < NP) L.BS[ord] = b;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; j++) s = fma(a[j], L.BS[j], s);
+    if (ord < NP) L.XS[ord] = s;
+    __syncthreads();
+    const double x = tid < NP ? L.XS[tid] : 0.0;
+    __syncthreads();
+    return x;
+}
+
+template <int W, int NP, int NWIN, int WIN>
+struct Ros4Coop {
+    static constexpr double qinv = 0.25;
+    __device__ static bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
+                                double &e) {
+        double a[NP];
+        double f;
+        const double dg = 1.0 / (Ros4::gamma * h);
+        iteration_rows<W, NP, NWIN, WIN>(M, L, y, P, dg, a, f);
+        int ord;
+        const bool ok = gj_invert<W, NP>(a, L, ord);
+        const double ih = 1.0 / h;
+        const double u1 = gj_apply<W, NP>(a, L, ord, f);
+        double ft = rhs<W>(M, L, y + Ros4::a21 * u1, P);
+        const double u2 = gj_apply<W, NP>(a, L, ord, ft + (Ros4::c21 * u1) * ih);
+        ft = rhs<W>(M, L, y + Ros4::a31 * u1 + Ros4::a32 * u2, P);
+        const double u3 = gj_apply<W, NP>(a, L, ord, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
+        const double u4 =
+            gj_apply<W, NP>(a, L, ord, ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
+        ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
+        e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
+        return ok;
+    }
+};
+
+// Algorithm 1 for one reactor on the group (same specification as the other kernels).
+template <int W, class S>
+__device__ void integrate_reactor(const DevMech &M, const Lds &L, int64_t r, double *y, int64_t ld, const double *p,
+                                  const double *t_end, double *t_io, double *h_io, const IntOpts &o, int32_t *status,
+                                  int32_t *nacc, int32_t *nrej) {
+    using G = Grp<W>;
+    const int N = M.N;
+    const int tid = G::tid();
+    const bool mine = tid < N;
+    double yv = mine ? y[int64_t(tid) * ld + r] : 0.0;
+    const double P = p[r];
+    const double te = t_end[r];
+    double t = t_io ? t_io[r] : 0.0;
+    double h = h_io ? h_io[r] : 0.0;
+    int st = CK_ST_OK;
+    int na = 0, nj = 0;
+    auto all_finite = [&](double v) {
+        return G::sum((mine && !isfinite(v)) ? 1.0 : 0.0, L.RED) == 0.0;
+    };
+    auto wsq = [&](double v) { return G::sum(mine ? v * v : 0.0, L.RED); };
+    if (!all_finite(yv)) {
+        st = CK_ST_NONFINITE;
+        h = 0.0;
+    } else if (o.h_fixed > 0.0) {
+        h = o.h_fixed;
+    } else if (!(h > 0.0)) {
+        if (o.h0 > 0.0) {
+            h = o.h0;
+        } else if (t < te) {
+            const double f0 = rhs<W>(M, L, yv, P);
+            if (!all_finite(f0)) {
+                st = CK_ST_NONFINITE;
+                h = 0.0;
+            } else {
+                const double sc = o.atol + o.rtol * fabs(yv);
+                const double d0 = sqrt(wsq(yv / sc) / N), d1 = sqrt(wsq(f0 / sc) / N);
+                const double span = te - t;
+                double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+                h0 = fmin(h0, span);
+                const double f1 = rhs<W>(M, L, yv + h0 * f0, P);
+                const double d2 = sqrt(wsq((f1 - f0) / sc) / N) / h0;
+                const double dm = fmax(d1, d2);
+                const double h1 = dm <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / dm, 0.2);
+                h = fmin(fmin(100.0 * h0, h1), span);
+            }
+        }
+    }
+    if (st == CK_ST_OK) {
+        while (t < te) {
+            if (int64_t(na) + nj >= o.max_steps) {
+                st = CK_ST_MAX_STEPS;
+                break;
+            }
+            const bool clipped = (t + h >= te);
+            const double hs = clipped ? te - t : h;
+            double yn, e;
+            const bool ok = S::step(M, L, yv, P, hs, yn, e);
+            double err;
+            if (o.h_fixed > 0.0)
+                err = 0.0;
+            else if (!ok)
+                err = INFINITY;
+            else {
+                const double sc = o.atol + o.rtol * fmax(fabs(yv), fabs(yn));
+                err = sqrt(wsq(e / sc) / N);
+                if (!all_finite(yn)) err = INFINITY;
+            }
+            const bool acc = err < 1.0;
+            if (acc) {
+                yv = yn;
+                t = clipped ? te : t + hs;
+                na++;
+            } else {
+                nj++;
+            }
+            const double fac = o.h_fixed > 0.0 ? 1.0 : step_factor(err, S::qinv, acc);
+            h = hs * fac;
+            if (t < te && h < h_floor(t)) {
+                st = CK_ST_H_UNDERFLOW;
+                break;
+            }
+        }
+    }
+    if (mine) y[int64_t(tid) * ld + r] = yv;
+    if (tid == 0) {
+        if (t_io) t_io[r] = t;
+        if (h_io) h_io[r] = h;
+        status[r] = st;
+        nacc[r] = na;
+        nrej[r] = nj;
+    }
+}
+
+template <int W, class S, int WIN>
+__global__ void __launch_bounds__(64 * W) coop_kernel(DevMech M, int64_t n, double *y, int64_t ld, const double *p,
+                                                      const double *t_end, double *t_io, double *h_io, IntOpts o,
+                                                      unsigned *queue, int32_t *status, int32_t *nacc,
+                                                      int32_t *nrej) {
+    extern __shared__ double lds_raw[];
+    const Lds L = carve(lds_raw, M.nsp, WIN);
+    init_lds(M, L, int(threadIdx.x), 64 * W);
+    __shared__ int64_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = int64_t(atomicAdd(queue, 1u));
+        __syncthreads();
+        const int64_t r = next;
+        __syncthreads();
+        if (r >= n) break;
+        integrate_reactor<W, S>(M, L, r, y, ld, p, t_end, t_io, h_io, o, status, nacc, nrej);
+        __syncthreads();
+    }
+}
+
+__global__ void zero_queue_kernel(unsigned *q) { *q = 0u; }
+
+template <int W, int NP, int NWIN, int WIN>
+int launch(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end, double *t,
+           double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc, int32_t *nrej,
+           hipStream_t s) {
+    using S = Ros4Coop<W, NP, NWIN, WIN>;
+    const size_t lds = lds_doubles(M.nsp, WIN) * sizeof(double);
+    auto kern = coop_kernel<W, S, WIN>;
+    if (lds > 64 * 1024 && hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+        return CK_EHIP;
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CK_EHIP;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return CK_EHIP;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * W, lds) != hipSuccess || per < 1)
+        return CK_EHIP;
+    int64_t grid = int64_t(cus) * per;
+    if (grid > n) grid = n;
+    zero_queue_kernel<<<1, 1, 0, s>>>(queue);
+    kern<<<dim3(unsigned(grid)), dim3(64 * W), lds, s>>>(M, n, y, ld, p, t_end, t, h, o, queue, status, nacc, nrej);
+    return hipGetLastError() == hipSuccess ? CK_OK : CK_EHIP;
+}
+
+}  // namespace coop
+
+bool coop_supported(const DevMech &M) { return M.N <= 128; }
+
+int launch_integrate_coop(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end,
+                          double *t, double *h, const IntOpts &o, void *ws, int32_t *status, int32_t *nacc,
+                          int32_t *nrej, hipStream_t s) {
+    unsigned *q = static_cast<unsigned *>(ws);
+    const int np = ((M.N + 7) / 8) * 8;
+#define CK_COOP1(NPV) \
+    case NPV: return coop::launch<1, NPV, 1, NPV>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+#define CK_COOP2(NPV) \
+    case NPV: return coop::launch<2, NPV, 2, NPV / 2>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+    switch (np) {
+        CK_COOP1(8) CK_COOP1(16) CK_COOP1(24) CK_COOP1(32) CK_COOP1(40) CK_COOP1(48) CK_COOP1(56) CK_COOP1(64)
+        CK_COOP2(72) CK_COOP2(80) CK_COOP2(88) CK_COOP2(96) CK_COOP2(104) CK_COOP2(112) CK_COOP2(120)
+        CK_COOP2(128)
+        default: return CK_EUNSUPPORTED;
+    }
+#undef CK_COOP1
+#undef CK_COOP2
+}
+
+}  // namespace ck

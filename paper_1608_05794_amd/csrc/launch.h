@@ -33,4 +33,10 @@ int launch_integrate_wave(int method, const DevMech &M, int64_t n, double *y, in
                           const double *t_end, double *t, double *h, const IntOpts &o, void *ws,
                           int32_t *status, int32_t *nacc, int32_t *nrej, hipStream_t s);
 
+// workgroup-cooperative ROS4 (k_coop.hip)
+bool coop_supported(const DevMech &M);
+int launch_integrate_coop(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end,
+                          double *t, double *h, const IntOpts &o, void *ws, int32_t *status, int32_t *nacc,
+                          int32_t *nrej, hipStream_t s);
+
 }  // namespace ck

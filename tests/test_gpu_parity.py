@@ -139,17 +139,27 @@ def test_rkf45_parity_m111_two_slots(ck, gmech, oracle_mech):
 
 
 def test_ros4_m111_lane(ck, gmech, oracle_mech):
-    """N = 112 through the lane kernel (the wavefront ROS4 holds one matrix row per lane, N <= 64)."""
+    """N = 112 through the lane kernel."""
     g, om = gmech("M111"), oracle_mech("M111")
     y, P = synth.reactor_states(om.n_species, 5, "divergent", seed=1005)
     # a fixed budget of 12 attempted steps (the lane kernel is latency-bound at this batch size)
-    res, orc = _integrate_both(ck, g, om, y, P, 1e-3, "ros4", "auto", max_steps=12)
+    res, orc = _integrate_both(ck, g, om, y, P, 1e-3, "ros4", "lane", max_steps=12)
     assert np.array_equal(res["status"], orc["status"]) and np.all(res["status"] == 1)
-    _report_and_check(f"ros4 M111 auto", res, orc)
+    _report_and_check(f"ros4 M111 lane", res, orc)
 
 
-@pytest.mark.parametrize("method", ["ros4", "rkf45"])
-@pytest.mark.parametrize("kernel", ["wave", "lane"])
+@pytest.mark.parametrize("name,n,te", [("M13", 300, 1e-4), ("M53", 67, 2e-6), ("M111", 24, 2e-7)])
+def test_ros4_group_parity(ck, gmech, oracle_mech, name, n, te):
+    """Workgroup kernel: one wavefront per reactor for N <= 64, two for N = 112 (Gauss-Jordan inverse)."""
+    g, om = gmech(name), oracle_mech(name)
+    y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=1009)
+    res, orc = _integrate_both(ck, g, om, y, P, te, "ros4", "group")
+    assert np.array_equal(res["status"], orc["status"])
+    _report_and_check(f"ros4 group {name}", res, orc)
+
+
+@pytest.mark.parametrize("method,kernel", [("ros4", "wave"), ("ros4", "lane"), ("ros4", "group"),
+                                           ("rkf45", "wave"), ("rkf45", "lane")])
 def test_edge_cases(ck, gmech, oracle_mech, method, kernel):
     g, om = gmech("M13"), oracle_mech("M13")
     y, P = synth.reactor_states(om.n_species, 65, "small", seed=1006)
@@ -172,7 +182,7 @@ def test_edge_cases(ck, gmech, oracle_mech, method, kernel):
     assert weighted_error(res["y"], orc["y"]) <= 1e-9
 
 
-@pytest.mark.parametrize("kernel", ["wave", "lane"])
+@pytest.mark.parametrize("kernel", ["wave", "lane", "group"])
 def test_resume_and_batch_independence(ck, gmech, kernel):
     """(t, h, y) resume is bitwise; a reactor's result does not depend on its batch (Section 4: scalar and
     SIMD results agree)."""
