@@ -94,7 +94,7 @@ def parse():
     ap.add_argument("--mech", default="M53")
     ap.add_argument("--reactors", type=int, default=131072)
     ap.add_argument("--t-end", type=float, default=1e-3)
-    ap.add_argument("--kernel", default="wave", choices=["wave", "lane", "auto"])
+    ap.add_argument("--kernel", default="wave", choices=["wave", "lane", "group", "auto"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refine"])
     ap.add_argument("--launch-steps", type=int, default=2000,
                     help="attempted steps per reactor per kernel launch; launches resume from (t, h)")
