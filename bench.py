@@ -23,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "reactors/s integrated (ROS4, rtol 1e-8), RHS evals/s, p50/p99 solve latency"
+KERNEL_NAMES = {"wave": "integrate_wave_kernel<Ros4Adapter>", "auto": "integrate_wave_kernel<Ros4Adapter>",
+                "group": "coop_kernel<Ros4Coop>", "lane": "integrate_lane_kernel<0>"}
 PEAK_FP64_VECTOR = 78.6e12          # FLOP/s, MI355X FP64 vector (VALU)
 TRANSCENDENTAL_FLOPS = 20           # FP64 operations charged per exp / log / log10 / exp10
 
@@ -103,6 +105,8 @@ def parse():
     ap.add_argument("--rhs-batches", type=int, default=8, help="distinct state batches cycled in the RHS leg")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 8 per host core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device three times (counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -129,6 +133,17 @@ def main():
               "MI355X; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8,
+                          "dispatches": 3}), flush=True)
+        return
 
     from paper_1608_05794_amd import ck, synth
 
@@ -232,8 +247,9 @@ def main():
         "status_counts": {"ok": status[0], "max_steps": status[1], "h_underflow": status[2], "nonfinite": status[3]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": None,
-                     "kernel": "integrate_wave_kernel<Ros4Adapter>" if a.kernel != "lane" else
-                     "integrate_lane_kernel<0>",
+                     "kernel": KERNEL_NAMES[a.kernel].replace("Adapter", "Adapter32" if a.precision != "fp64" else "Adapter"),
+                     "launches": launches,
+                     "avg_launch_ms": 1e3 * kernel_s / launches,
                      "flops_per_step_of_batch": flops_launch, "kernel_s": kernel_s,
                      "flops_per_step": fl["ros4_step"]},
     }

@@ -74,11 +74,12 @@ typedef struct {
     int32_t kernel;        /* CK_KERNEL_* */
     int32_t precision;     /* CK_PREC_* (ROS4 only) */
     int32_t refine_sweeps; /* FP32 mode: maximum FP64 refinement sweeps, 0..3 */
-    int32_t reserved;
+    int32_t blocks_per_cu; /* persistent kernels (WAVE, GROUP): resident workgroups per compute unit;
+                              0 = as many as registers and LDS allow (larger values are clamped) */
 } ck_opts;
 
 /* Fills *o with the defaults: rtol 1e-8, atol 1e-12, h0 0, h_fixed 0, max_steps 1e6,
- * CK_KERNEL_AUTO, CK_PREC_FP64, refine_sweeps 3. */
+ * CK_KERNEL_AUTO, CK_PREC_FP64, refine_sweeps 3, blocks_per_cu 0. */
 void ck_opts_default(ck_opts *o);
 
 const char *ck_strerror(int code);
@@ -118,6 +119,11 @@ int ck_jacobian_eval(const ck_mech *m, int64_t n, const double *y, int64_t ld, c
  * Bytes of device workspace that ck_integrate_* needs for n reactors with
  * options o (NULL = defaults).  Pass a buffer at least this large as
  * `workspace`, or NULL to let the library allocate (and cache) its own.
+ * Lane kernel: per-reactor scratch, linear in n.  Wavefront kernel: a
+ * 256-byte queue counter.  Workgroup kernel with N > 64: the counter plus
+ * the parked Gauss-Jordan inverses of the resident workgroups (2 per compute
+ * unit of the mechanism's device, 128 N' doubles each with N' = N rounded up
+ * to a multiple of 8), independent of n.  Returns 0 on a device query error.
  */
 size_t ck_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts *o);
 

@@ -61,6 +61,7 @@ int validate_opts(const ck_opts *o, IntOpts &io) {
     if (o->kernel < CK_KERNEL_AUTO || o->kernel > CK_KERNEL_GROUP) return CK_EINVAL;
     if (o->precision != CK_PREC_FP64 && o->precision != CK_PREC_FP32_REFINE) return CK_EINVAL;
     if (o->refine_sweeps < 0 || o->refine_sweeps > 3) return CK_EINVAL;
+    if (o->blocks_per_cu < 0) return CK_EINVAL;
     io.rtol = o->rtol;
     io.atol = o->atol;
     io.h0 = o->h0;
@@ -68,6 +69,7 @@ int validate_opts(const ck_opts *o, IntOpts &io) {
     io.max_steps = o->max_steps;
     io.precision = o->precision;
     io.refine_sweeps = o->refine_sweeps;
+    io.blocks_per_cu = o->blocks_per_cu;
     return CK_OK;
 }
 
@@ -137,7 +139,7 @@ extern "C" void ck_opts_default(ck_opts *o) {
     o->kernel = CK_KERNEL_AUTO;
     o->precision = CK_PREC_FP64;
     o->refine_sweeps = 3;
-    o->reserved = 0;
+    o->blocks_per_cu = 0;
 }
 
 extern "C" const char *ck_strerror(int code) {
@@ -204,7 +206,13 @@ extern "C" size_t ck_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts 
         const int k = choose_kernel(m, method, o);
         size_t b = 256;
         if (k == CK_KERNEL_LANE) b = lane_bytes(m, n, method);
-        else if (k == CK_KERNEL_WAVE || k == CK_KERNEL_GROUP) b = wave_ws_bytes(m->dev, n);
+        else if (k == CK_KERNEL_WAVE) b = wave_ws_bytes(m->dev, n);
+        else if (k == CK_KERNEL_GROUP) {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess)
+                return 0;
+            b = coop_ws_bytes(m->dev, cus);
+        }
         if (b > best) best = b;
     }
     return best;

@@ -11,6 +11,10 @@
 //     pivot column is always register 0 and the loop body is the same code for
 //     every step (a runtime loop, small code).  The four stage solves of a
 //     step are then matrix-vector products with no sequential substitution.
+//   - with two wavefronts (N > 64) a thread's row of the inverse (up to 128
+//     doubles) is parked in a per-workgroup slice of the workspace while the
+//     stage right-hand sides are evaluated, so the source-term code does not
+//     have to share the register file with it.
 // Reactors come from the same device work queue as the wavefront kernels.
 #include "ck_internal.h"
 #include "kinetics.h"
@@ -38,6 +42,7 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
 //   JC[ns * ldj + 128] TB[ns] DWT[ns] TROW[ns + 128]
 struct Lds {
     double *C, *G, *H, *WD, *IW, *VX, *RED, *PB, *BS, *XS, *JC, *TB, *DWT, *TROW;
+    double *rows;   // parked inverse of this workgroup ([NP][64 W], global memory), or null
     int ldj;
 };
 
@@ -64,6 +69,7 @@ __device__ Lds carve(double *b, int ns, int win) {
     L.TB = b; b += ns;
     L.DWT = b; b += ns;
     L.TROW = b;
+    L.rows = nullptr;
     return L;
 }
 
@@ -392,9 +398,34 @@ __device__ double gj_apply(const double (&a)[NP], const Lds &L, int ord, double 
     return x;
 }
 
-template <int W, int NP, int NWIN, int WIN>
+// Same product with the inverse read back from its parked copy (column j of the rotated row of
+// thread t at rows[j * 64 W + t]: consecutive threads read consecutive addresses).
+template <int W, int NP>
+__device__ double gj_apply_parked(const Lds &L, int ord, double b) {
+    using G = Grp<W>;
+    const int tid = G::tid();
+    if (ord < NP) L.BS[ord] = b;
+    __syncthreads();
+    double s = 0.0;
+    if (ord < NP) {
+        const double *r = L.rows + tid;
+#pragma unroll 8
+        for (int j = 0; j < NP; j++) s = fma(r[j * G::T], L.BS[j], s);
+        L.XS[ord] = s;
+    }
+    __syncthreads();
+    const double x = tid < NP ? L.XS[tid] : 0.0;
+    __syncthreads();
+    return x;
+}
+
+template <int W, int NP, int NWIN, int WIN, bool PARK>
 struct Ros4Coop {
     static constexpr double qinv = 0.25;
+    static constexpr size_t kRows = size_t(NP) * 64 * W;   // parked doubles per workgroup
+    __device__ static double apply(const double (&a)[NP], const Lds &L, int ord, double b) {
+        return PARK ? gj_apply_parked<W, NP>(L, ord, b) : gj_apply<W, NP>(a, L, ord, b);
+    }
     __device__ static bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
                                 double &e) {
         double a[NP];
@@ -403,14 +434,18 @@ struct Ros4Coop {
         iteration_rows<W, NP, NWIN, WIN>(M, L, y, P, dg, a, f);
         int ord;
         const bool ok = gj_invert<W, NP>(a, L, ord);
+        if (PARK && ord < NP) {
+            double *r = L.rows + Grp<W>::tid();
+#pragma unroll
+            for (int j = 0; j < NP; j++) r[j * Grp<W>::T] = a[j];
+        }
         const double ih = 1.0 / h;
-        const double u1 = gj_apply<W, NP>(a, L, ord, f);
+        const double u1 = apply(a, L, ord, f);
         double ft = rhs<W>(M, L, y + Ros4::a21 * u1, P);
-        const double u2 = gj_apply<W, NP>(a, L, ord, ft + (Ros4::c21 * u1) * ih);
+        const double u2 = apply(a, L, ord, ft + (Ros4::c21 * u1) * ih);
         ft = rhs<W>(M, L, y + Ros4::a31 * u1 + Ros4::a32 * u2, P);
-        const double u3 = gj_apply<W, NP>(a, L, ord, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
-        const double u4 =
-            gj_apply<W, NP>(a, L, ord, ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
+        const double u3 = apply(a, L, ord, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
+        const double u4 = apply(a, L, ord, ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
         ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
         e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
         return ok;
@@ -513,10 +548,11 @@ __device__ void integrate_reactor(const DevMech &M, const Lds &L, int64_t r, dou
 template <int W, class S, int WIN>
 __global__ void __launch_bounds__(64 * W) coop_kernel(DevMech M, int64_t n, double *y, int64_t ld, const double *p,
                                                       const double *t_end, double *t_io, double *h_io, IntOpts o,
-                                                      unsigned *queue, int32_t *status, int32_t *nacc,
-                                                      int32_t *nrej) {
+                                                      unsigned *queue, double *park, int32_t *status,
+                                                      int32_t *nacc, int32_t *nrej) {
     extern __shared__ double lds_raw[];
-    const Lds L = carve(lds_raw, M.nsp, WIN);
+    Lds L = carve(lds_raw, M.nsp, WIN);
+    if (park) L.rows = park + size_t(blockIdx.x) * S::kRows;
     init_lds(M, L, int(threadIdx.x), 64 * W);
     __shared__ int64_t next;
     for (;;) {
@@ -532,11 +568,15 @@ __global__ void __launch_bounds__(64 * W) coop_kernel(DevMech M, int64_t n, doub
 
 __global__ void zero_queue_kernel(unsigned *q) { *q = 0u; }
 
+// Workgroups per CU of a parking kernel are capped so that the parked rows fit the workspace.
+constexpr int kParkBlocksPerCu = 2;
+
 template <int W, int NP, int NWIN, int WIN>
 int launch(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end, double *t,
            double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc, int32_t *nrej,
            hipStream_t s) {
-    using S = Ros4Coop<W, NP, NWIN, WIN>;
+    constexpr bool PARK = W > 1;
+    using S = Ros4Coop<W, NP, NWIN, WIN, PARK>;
     const size_t lds = lds_doubles(M.nsp, WIN) * sizeof(double);
     auto kern = coop_kernel<W, S, WIN>;
     if (lds > 64 * 1024 && hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -547,16 +587,26 @@ int launch(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, 
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return CK_EHIP;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * W, lds) != hipSuccess || per < 1)
         return CK_EHIP;
+    if (o.blocks_per_cu > 0 && o.blocks_per_cu < per) per = o.blocks_per_cu;
+    if (PARK && per > kParkBlocksPerCu) per = kParkBlocksPerCu;
     int64_t grid = int64_t(cus) * per;
     if (grid > n) grid = n;
+    double *park = PARK ? reinterpret_cast<double *>(reinterpret_cast<char *>(queue) + 256) : nullptr;
     zero_queue_kernel<<<1, 1, 0, s>>>(queue);
-    kern<<<dim3(unsigned(grid)), dim3(64 * W), lds, s>>>(M, n, y, ld, p, t_end, t, h, o, queue, status, nacc, nrej);
+    kern<<<dim3(unsigned(grid)), dim3(64 * W), lds, s>>>(M, n, y, ld, p, t_end, t, h, o, queue, park, status, nacc,
+                                                         nrej);
     return hipGetLastError() == hipSuccess ? CK_OK : CK_EHIP;
 }
 
 }  // namespace coop
 
 bool coop_supported(const DevMech &M) { return M.N <= 128; }
+
+size_t coop_ws_bytes(const DevMech &M, int cus) {
+    if (M.N <= 64) return 256;
+    const size_t np = size_t((M.N + 7) / 8) * 8;
+    return 256 + size_t(cus) * coop::kParkBlocksPerCu * np * 128 * sizeof(double);
+}
 
 int launch_integrate_coop(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end,
                           double *t, double *h, const IntOpts &o, void *ws, int32_t *status, int32_t *nacc,

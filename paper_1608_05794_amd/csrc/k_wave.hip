@@ -847,6 +847,7 @@ int launch_int(const DevMech &M, int64_t n, double *y, int64_t ld, const double 
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return CK_EHIP;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, integrate_wave_kernel<S>, 64, lds) != hipSuccess || per < 1)
         return CK_EHIP;
+    if (o.blocks_per_cu > 0 && o.blocks_per_cu < per) per = o.blocks_per_cu;
     int64_t grid = int64_t(cus) * per;
     if (grid > n) grid = n;
     zero_u32_kernel<<<1, 1, 0, s>>>(queue);

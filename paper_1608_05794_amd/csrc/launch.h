@@ -9,7 +9,7 @@ namespace ck {
 struct IntOpts {
     double rtol, atol, h0, h_fixed;
     int64_t max_steps;
-    int32_t precision, refine_sweeps;
+    int32_t precision, refine_sweeps, blocks_per_cu;
 };
 
 // lane-per-reactor family (k_lane.hip)
@@ -35,6 +35,7 @@ int launch_integrate_wave(int method, const DevMech &M, int64_t n, double *y, in
 
 // workgroup-cooperative ROS4 (k_coop.hip)
 bool coop_supported(const DevMech &M);
+size_t coop_ws_bytes(const DevMech &M, int cus);   // queue counter + parked inverse rows
 int launch_integrate_coop(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end,
                           double *t, double *h, const IntOpts &o, void *ws, int32_t *status, int32_t *nacc,
                           int32_t *nrej, hipStream_t s);
