@@ -16,8 +16,12 @@ BUILD = os.path.join(HERE, "_build")
 SOURCES = ["mech.hip", "k_lane.hip", "k_wave.hip", "k_coop.hip", "api.hip"]
 ARCH = os.environ.get("CK_OFFLOAD_ARCH", "gfx950")
 
+# -disable-machine-licm: keeps the backend from hoisting FP64 constants (the exp / log polynomial
+# coefficients) and addresses out of the per-reaction loops into long-lived registers; in these
+# kernels that hoisting costs far more in register spills and occupancy than it saves.
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", os.path.join(HERE, "..", "include")]
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-disable-machine-licm",
+          "-I", os.path.join(HERE, "..", "include")]
 
 
 def _compile(src, verbose):

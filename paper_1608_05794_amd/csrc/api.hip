@@ -206,12 +206,11 @@ extern "C" size_t ck_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts 
         const int k = choose_kernel(m, method, o);
         size_t b = 256;
         if (k == CK_KERNEL_LANE) b = lane_bytes(m, n, method);
-        else if (k == CK_KERNEL_WAVE) b = wave_ws_bytes(m->dev, n);
-        else if (k == CK_KERNEL_GROUP) {
+        else if (k == CK_KERNEL_WAVE || k == CK_KERNEL_GROUP) {
             int cus = 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess)
                 return 0;
-            b = coop_ws_bytes(m->dev, cus);
+            b = k == CK_KERNEL_WAVE ? wave_ws_bytes(m->dev, cus) : coop_ws_bytes(m->dev, cus);
         }
         if (b > best) best = b;
     }

@@ -21,7 +21,7 @@
 #include "launch.h"
 
 extern "C" __device__ unsigned long long __ockl_wfred_max_u64(unsigned long long);
-extern "C" __device__ double __ockl_wfred_add_f64(double);
+extern "C" __device__ __forceinline__ double __ockl_wfred_add_f64(double);
 
 namespace ck {
 namespace coop {
@@ -52,7 +52,7 @@ __host__ __device__ inline size_t lds_doubles(int ns, int win) {
            2 * size_t(ns) + size_t(ns) + 128;
 }
 
-__device__ Lds carve(double *b, int ns, int win) {
+__device__ __forceinline__ Lds carve(double *b, int ns, int win) {
     Lds L;
     L.ldj = ldj_of(win);
     L.C = b; b += ns + 1;
@@ -77,10 +77,10 @@ __device__ Lds carve(double *b, int ns, int win) {
 template <int W>
 struct Grp {
     static constexpr int T = 64 * W;
-    __device__ static int tid() { return opaque(int(threadIdx.x)); }
-    __device__ static int lane() { return int(threadIdx.x) & 63; }
-    __device__ static int wave() { return __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6); }
-    __device__ static double sum(double v, double *red) {
+    __device__ static __forceinline__ int tid() { return opaque(int(threadIdx.x)); }
+    __device__ static __forceinline__ int lane() { return int(threadIdx.x) & 63; }
+    __device__ static __forceinline__ int wave() { return __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6); }
+    __device__ static __forceinline__ double sum(double v, double *red) {
         const double s = __ockl_wfred_add_f64(v);
         if (W == 1) return s;
         if (lane() == 0) red[wave()] = s;
@@ -92,7 +92,7 @@ struct Grp {
         return t;
     }
     // value of thread src (src uniform)
-    __device__ static double bcast(double v, int src, double *slot) {
+    __device__ static __forceinline__ double bcast(double v, int src, double *slot) {
         if (W == 1) return readlane_d(v, src);
         if (int(threadIdx.x) == src) *slot = v;
         __syncthreads();
@@ -101,7 +101,7 @@ struct Grp {
         return r;
     }
     // thread holding the largest key (lowest thread index on ties) and the key itself
-    __device__ static int argmax(unsigned long long key, double *xs, unsigned long long &best) {
+    __device__ static __forceinline__ int argmax(unsigned long long key, double *xs, unsigned long long &best) {
         const unsigned long long mx = __ockl_wfred_max_u64(key);
         const int l = __builtin_ctzll(__ballot(key == mx));
         if (W == 1) {
@@ -127,7 +127,7 @@ struct Grp {
     }
 };
 
-__device__ void init_lds(const DevMech &M, const Lds &L, int tid, int nthreads) {
+__device__ __forceinline__ void init_lds(const DevMech &M, const Lds &L, int tid, int nthreads) {
     for (int e = tid; e < 128; e += nthreads) {
         L.IW[e] = e < M.nsp ? M.invW()[e] : 0.0;
         L.VX[e] = 0.0;
@@ -145,7 +145,7 @@ __device__ __forceinline__ int species_of(int tid, int ns) { return (tid >= 1 &&
 
 // Mixture state and species thermodynamics (Section 3); zeroes the accumulators.
 template <int W, bool JAC>
-__device__ void species_pass(const DevMech &M, double y, double P, const Lds &L, Mix &x) {
+__device__ __forceinline__ void species_pass(const DevMech &M, double y, double P, const Lds &L, Mix &x) {
     using G = Grp<W>;
     const int ns = M.nsp, tid = G::tid();
     const int k = species_of(tid, ns);
@@ -180,7 +180,7 @@ __device__ void species_pass(const DevMech &M, double y, double P, const Lds &L,
 
 // Rates of progress into WD (FIRST window only) and d wdot/dC for columns [c0, c0 + win) into JC.
 template <int W, bool JAC>
-__device__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, double Ctot, int c0, int win, bool first) {
+__device__ __forceinline__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, double Ctot, int c0, int win, bool first) {
     using G = Grp<W>;
     const int nr = M.nrxn, ns = M.nsp, tid = G::tid();
     if (JAC) {
@@ -246,7 +246,7 @@ __device__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, dou
 
 // Eqs. ydot and tdot.
 template <int W>
-__device__ double finish_rhs(const DevMech &M, const Lds &L, const Mix &x) {
+__device__ __forceinline__ double finish_rhs(const DevMech &M, const Lds &L, const Mix &x) {
     using G = Grp<W>;
     const int tid = G::tid();
     const int k = species_of(tid, M.nsp);
@@ -262,7 +262,7 @@ __device__ double finish_rhs(const DevMech &M, const Lds &L, const Mix &x) {
 }
 
 template <int W>
-__device__ double rhs(const DevMech &M, const Lds &L, double y, double P) {
+__device__ __forceinline__ double rhs(const DevMech &M, const Lds &L, double y, double P) {
     Mix x;
     species_pass<W, false>(M, y, P, L, x);
     reaction_pass<W, false>(M, L, x.t, x.Ctot, 0, 0, true);
@@ -274,7 +274,7 @@ __device__ double rhs(const DevMech &M, const Lds &L, double y, double P) {
 // f(y) and this thread's row of M = dg I - J in registers (NP columns), d wdot/dC staged in NWIN
 // column windows of width WIN.
 template <int W, int NP, int NWIN, int WIN>
-__device__ void iteration_rows(const DevMech &M, const Lds &L, double y, double P, double dg, double (&a)[NP],
+__device__ __forceinline__ void iteration_rows(const DevMech &M, const Lds &L, double y, double P, double dg, double (&a)[NP],
                                double &f) {
     using G = Grp<W>;
     const int ns = M.nsp;
@@ -347,7 +347,7 @@ __device__ void iteration_rows(const DevMech &M, const Lds &L, double y, double 
 // whose pivot order is k holds row k of M^-1 with columns permuted: a[j] = Minv[k][p_j], p_j the
 // thread that was pivot j.  Threads with index >= NP hold no row.
 template <int W, int NP>
-__device__ bool gj_invert(double (&a)[NP], const Lds &L, int &ord) {
+__device__ __forceinline__ bool gj_invert(double (&a)[NP], const Lds &L, int &ord) {
     using G = Grp<W>;
     const int tid = G::tid();
     bool done = tid >= NP;
@@ -383,7 +383,7 @@ __device__ bool gj_invert(double (&a)[NP], const Lds &L, int &ord) {
 
 // x = M^-1 b with the rotated inverse; b and x one component per thread.
 template <int W, int NP>
-__device__ double gj_apply(const double (&a)[NP], const Lds &L, int ord, double b) {
+__device__ __forceinline__ double gj_apply(const double (&a)[NP], const Lds &L, int ord, double b) {
     using G = Grp<W>;
     const int tid = G::tid();
     if (ord < NP) L.BS[ord] = b;
@@ -401,7 +401,7 @@ __device__ double gj_apply(const double (&a)[NP], const Lds &L, int ord, double 
 // Same product with the inverse read back from its parked copy (column j of the rotated row of
 // thread t at rows[j * 64 W + t]: consecutive threads read consecutive addresses).
 template <int W, int NP>
-__device__ double gj_apply_parked(const Lds &L, int ord, double b) {
+__device__ __forceinline__ double gj_apply_parked(const Lds &L, int ord, double b) {
     using G = Grp<W>;
     const int tid = G::tid();
     if (ord < NP) L.BS[ord] = b;
@@ -423,10 +423,10 @@ template <int W, int NP, int NWIN, int WIN, bool PARK>
 struct Ros4Coop {
     static constexpr double qinv = 0.25;
     static constexpr size_t kRows = size_t(NP) * 64 * W;   // parked doubles per workgroup
-    __device__ static double apply(const double (&a)[NP], const Lds &L, int ord, double b) {
+    __device__ static __forceinline__ double apply(const double (&a)[NP], const Lds &L, int ord, double b) {
         return PARK ? gj_apply_parked<W, NP>(L, ord, b) : gj_apply<W, NP>(a, L, ord, b);
     }
-    __device__ static bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
                                 double &e) {
         double a[NP];
         double f;
@@ -454,7 +454,7 @@ struct Ros4Coop {
 
 // Algorithm 1 for one reactor on the group (same specification as the other kernels).
 template <int W, class S>
-__device__ void integrate_reactor(const DevMech &M, const Lds &L, int64_t r, double *y, int64_t ld, const double *p,
+__device__ __forceinline__ void integrate_reactor(const DevMech &M, const Lds &L, int64_t r, double *y, int64_t ld, const double *p,
                                   const double *t_end, double *t_io, double *h_io, const IntOpts &o, int32_t *status,
                                   int32_t *nacc, int32_t *nrej) {
     using G = Grp<W>;

@@ -16,7 +16,7 @@
 #include "launch.h"
 
 extern "C" __device__ unsigned long long __ockl_wfred_max_u64(unsigned long long);
-extern "C" __device__ double __ockl_wfred_add_f64(double);
+extern "C" __device__ __forceinline__ double __ockl_wfred_add_f64(double);
 extern "C" __device__ unsigned int __ockl_wfred_max_u32(unsigned int);
 
 namespace ck {
@@ -42,22 +42,26 @@ __device__ __forceinline__ bool wave_all(bool v) { return __ballot(!v) == 0ull; 
 // LDS layout of one wavefront (doubles):
 //   C[ns+1] G[ns] H[ns] WD[ns] | IW[64] (1/W_j padded with zeros) | VX[64] (broadcast scratch) |
 //   JC[ns*ldj + 64] TB[ns] DWT[ns] TROW[ns + 64]   (Jacobian kernels only)
+// JC holds d wdot / dC for a window of `win` consecutive columns (all ns columns when the
+// Jacobian is staged in one piece), leading dimension ldj = win | 1.
 // ---------------------------------------------------------------------------------------
 struct Lds {
     double *C, *G, *H, *WD, *IW, *VX, *JC, *TB, *DWT, *TROW;
+    double *park;   // this wavefront's slice of the workspace for parked LU rows ([NP][64]), or null
     int ldj;
 };
 
-__host__ __device__ inline int ldj_of(int ns) { return ns | 1; }
-__host__ __device__ inline size_t lds_doubles(int ns, bool jac) {
+__host__ __device__ inline int ldj_of(int win) { return win | 1; }
+__host__ __device__ inline size_t lds_doubles(int ns, bool jac, int win) {
     size_t d = size_t(ns + 1) + 3 * size_t(ns) + 128;
-    if (jac) d += size_t(ns) * ldj_of(ns) + 64 + 2 * size_t(ns) + size_t(ns) + 64;
+    if (jac) d += size_t(ns) * ldj_of(win) + 64 + 2 * size_t(ns) + size_t(ns) + 64;
     return d;
 }
+__host__ __device__ inline size_t lds_doubles(int ns, bool jac) { return lds_doubles(ns, jac, ns); }
 
-__device__ Lds carve(double *b, int ns, bool jac) {
+__device__ __forceinline__ Lds carve(double *b, int ns, bool jac, int win) {
     Lds L;
-    L.ldj = ldj_of(ns);
+    L.ldj = ldj_of(win);
     L.C = b; b += ns + 1;
     L.G = b; b += ns;
     L.H = b; b += ns;
@@ -72,10 +76,12 @@ __device__ Lds carve(double *b, int ns, bool jac) {
     } else {
         L.JC = L.TB = L.DWT = L.TROW = nullptr;
     }
+    L.park = nullptr;
     return L;
 }
+__device__ __forceinline__ Lds carve(double *b, int ns, bool jac) { return carve(b, ns, jac, ns); }
 
-__device__ void init_lds(const DevMech &M, const Lds &L) {
+__device__ __forceinline__ void init_lds(const DevMech &M, const Lds &L) {
     const int l = lane_id();
     L.IW[l] = l < M.nsp ? M.invW()[l] : 0.0;
     L.C[M.nsp] = 1.0;
@@ -100,8 +106,8 @@ __device__ __forceinline__ int slot_species(int c, int ns, int lane) {
 }
 
 // Mixture state and per-species thermodynamics (Section 3: ideal gas, Eq. tfits).
-template <int RPL, bool JAC>
-__device__ void species_pass(const DevMech &M, const double (&y)[RPL], double P, const Lds &L, Mix<RPL> &x) {
+template <int RPL, bool JAC, bool ZERO_JC = true>
+__device__ __forceinline__ void species_pass(const DevMech &M, const double (&y)[RPL], double P, const Lds &L, Mix<RPL> &x) {
     const int ns = M.nsp;
     const int lane = lane_fresh();
     const double T = bcast(y[0], 0);
@@ -138,7 +144,8 @@ __device__ void species_pass(const DevMech &M, const double (&y)[RPL], double P,
     if (JAC) {
         const int l = lane;
         const int tot = ns * L.ldj;
-        for (int e = l; e < tot; e += 64) L.JC[e] = 0.0;
+        if (ZERO_JC)
+            for (int e = l; e < tot; e += 64) L.JC[e] = 0.0;
         for (int e = l; e < ns; e += 64) {
             L.TB[e] = 0.0;
             L.DWT[e] = 0.0;
@@ -149,9 +156,12 @@ __device__ void species_pass(const DevMech &M, const double (&y)[RPL], double P,
 
 // Rates of progress (Eqs. wdot, kfor, krev, kc), scattered into WD; with JAC
 // also d wdot / dC (into JC, and the third-body rank-one part into TB) and
-// d wdot / dT at fixed C (into DWT).
+// d wdot / dT at fixed C (into DWT).  With a column window [c0, c0 + win) only
+// those columns of d wdot / dC are accumulated, and WD, TB and DWT only when
+// `first` is set.
 template <bool JAC>
-__device__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, double Ctot) {
+__device__ __forceinline__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, double Ctot, int c0, int win,
+                              bool first) {
     const int nr = M.nrxn;
     auto Cg = [&](int k) { return L.C[k]; };
     auto Gg = [&](int k) { return L.G[k]; };
@@ -164,39 +174,43 @@ __device__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, dou
         Rate q;
         reaction_rate<JAC>(M, R, S, nmax, t, Ctot, Cg, Gg, Hg, q);
         const double Rn = q.kf * q.pf - q.kr * q.pr;
-        const double qi = q.c * Rn;
+        if (first) {
+            const double qi = q.c * Rn;
 #pragma unroll
-        for (int s = 0; s < kMaxSlots; s++) {
-            if (s >= nmax) break;
-            if (S.sgn[s] != 0) atomicAdd(&L.WD[S.sp[s]], (S.sgn[s] * S.nu[s]) * qi);
+            for (int s = 0; s < kMaxSlots; s++) {
+                if (s >= nmax) break;
+                if (S.sgn[s] != 0) atomicAdd(&L.WD[S.sp[s]], (S.sgn[s] * S.nu[s]) * qi);
+            }
         }
         if (JAC) {
-            const double dqT = q.c * (q.kf * q.dlnkf * q.pf - q.kr * q.dlnkr * q.pr) + Rn * q.dcdT;
 #pragma unroll
             for (int b = 0; b < kMaxSlots; b++) {
                 if (b >= nmax) break;
-                if (S.sgn[b] == 0) continue;
+                const int col = S.sp[b] - c0;
+                if (S.sgn[b] == 0 || col < 0 || col >= win) continue;
                 const double d = dprod_slot(S, b, nmax);
                 const double dq = q.c * (S.sgn[b] < 0 ? q.kf * d : -q.kr * d);
 #pragma unroll
                 for (int a = 0; a < kMaxSlots; a++) {
                     if (a >= nmax) break;
-                    if (S.sgn[a] != 0) atomicAdd(&L.JC[S.sp[a] * L.ldj + S.sp[b]], (S.sgn[a] * S.nu[a]) * dq);
+                    if (S.sgn[a] != 0) atomicAdd(&L.JC[S.sp[a] * L.ldj + col], (S.sgn[a] * S.nu[a]) * dq);
                 }
             }
             const int eb = R.eff_begin, ec = rx_neff(R.meta);
+            const double dqT = q.c * (q.kf * q.dlnkf * q.pf - q.kr * q.dlnkr * q.pr) + Rn * q.dcdT;
 #pragma unroll
             for (int a = 0; a < kMaxSlots; a++) {
                 if (a >= nmax) break;
                 if (S.sgn[a] == 0) continue;
                 const double v = S.sgn[a] * S.nu[a];
-                atomicAdd(&L.DWT[S.sp[a]], v * dqT);
+                if (first) atomicAdd(&L.DWT[S.sp[a]], v * dqT);
                 if (q.dcdM != 0.0) {
                     const double base = v * Rn * q.dcdM;
-                    atomicAdd(&L.TB[S.sp[a]], base);
+                    if (first) atomicAdd(&L.TB[S.sp[a]], base);
                     for (int e = 0; e < ec; e++) {
                         const EffRec E = M.eff[eb + e];
-                        atomicAdd(&L.JC[S.sp[a] * L.ldj + E.sp], base * E.am1);
+                        const int col = E.sp - c0;
+                        if (col >= 0 && col < win) atomicAdd(&L.JC[S.sp[a] * L.ldj + col], base * E.am1);
                     }
                 }
             }
@@ -205,9 +219,14 @@ __device__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, dou
     __syncthreads();
 }
 
+template <bool JAC>
+__device__ __forceinline__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, double Ctot) {
+    reaction_pass<JAC>(M, L, t, Ctot, 0, M.nsp, true);
+}
+
 // Eqs. ydot and tdot from the accumulated production rates.
 template <int RPL>
-__device__ void finish_rhs(const DevMech &M, const Lds &L, const Mix<RPL> &x, double (&f)[RPL]) {
+__device__ __forceinline__ void finish_rhs(const DevMech &M, const Lds &L, const Mix<RPL> &x, double (&f)[RPL]) {
     const int ns = M.nsp;
     const int lane = lane_fresh();
     double qp = 0.0;
@@ -227,7 +246,7 @@ __device__ void finish_rhs(const DevMech &M, const Lds &L, const Mix<RPL> &x, do
 }
 
 template <int RPL>
-__device__ void rhs_wave(const DevMech &M, const Lds &L, const double (&y)[RPL], double P, double (&f)[RPL]) {
+__device__ __forceinline__ void rhs_wave(const DevMech &M, const Lds &L, const double (&y)[RPL], double P, double (&f)[RPL]) {
     Mix<RPL> x;
     species_pass<RPL, false>(M, y, P, L, x);
     reaction_pass<false>(M, L, x.t, x.Ctot);
@@ -242,7 +261,7 @@ struct JRow {
 };
 
 // Chain rule from (d wdot/dC, d wdot/dT) to J = df/dy (N <= 64, one row per lane).
-__device__ JRow jac_prepare(const DevMech &M, const Lds &L, const Mix<1> &x, double y0, double fT) {
+__device__ __forceinline__ JRow jac_prepare(const DevMech &M, const Lds &L, const Mix<1> &x, double y0, double fT) {
     const int ns = M.nsp, lane = lane_fresh();
     const int k = slot_species(0, ns, lane);
     const bool valid = k >= 0;
@@ -300,7 +319,7 @@ __device__ JRow jac_prepare(const DevMech &M, const Lds &L, const Mix<1> &x, dou
 // N <= NP <= 64.  The row descriptor jr stays valid (with the Jacobian pieces in LDS) until the
 // next Jacobian, so J x products can be formed later without a stored FP64 matrix.
 template <int NP, class T>
-__device__ void jac_rows(const DevMech &M, const Lds &L, double y, double P, double dg, T (&a)[NP], double &f,
+__device__ __forceinline__ void jac_rows(const DevMech &M, const Lds &L, double y, double P, double dg, T (&a)[NP], double &f,
                          JRow &jr) {
     Mix<1> x;
     const double yy[1] = {y};
@@ -317,8 +336,89 @@ __device__ void jac_rows(const DevMech &M, const Lds &L, double y, double P, dou
     __syncthreads();
 }
 
+// f(y) and this lane's row of M = dg I - J (FP64 registers) for N <= NP <= 64, with d wdot/dC
+// staged in NWIN column windows of WIN columns (NWIN * WIN >= ns).  The reaction pass runs once
+// per window (rates are recomputed), which keeps JC at ns * (WIN | 1) doubles of LDS; raw window
+// entries wait in the row registers until the chain-rule scalars of the row are known.
+template <int NP, int NWIN, int WIN>
+__device__ __forceinline__ void jac_rows_win(const DevMech &M, const Lds &L, double y, double P, double dg, double (&a)[NP],
+                             double &f) {
+    Mix<1> x;
+    const double yy[1] = {y};
+    double ff[1];
+    species_pass<1, true, false>(M, yy, P, L, x);
+    const int ns = M.nsp;
+    const int lane = lane_fresh();
+    const int k = lane - 1;
+    const bool valid = lane >= 1 && lane <= ns;
+    double jcc = 0.0, colH = 0.0;
+    for (int w = 0; w < NWIN; w++) {
+        const int c0 = opaque(w * WIN);
+        const int tot = ns * L.ldj;
+        for (int e = lane; e < tot; e += 64) L.JC[e] = 0.0;
+        __syncthreads();
+        reaction_pass<true>(M, L, x.t, x.Ctot, c0, WIN, w == 0);
+        if (w == 0) finish_rhs<1>(M, L, x, ff);
+        // raw d wdot_k / dC_(c0+j), parked in the workspace (column 1 + c0 + j of the row) until the
+        // chain-rule scalars of the row are known, so no row registers are live across a reaction pass
+        const double *row = &L.JC[(valid ? k : 0) * L.ldj];
+        double *pk = L.park + lane;
+        for (int j = 0; j < WIN && 1 + c0 + j < NP; j++) {
+            const bool in = c0 + j < ns;
+            const double v = (valid && in) ? row[j] : 0.0;
+            if (in) jcc += v * L.C[c0 + j];
+            pk[(1 + c0 + j) * 64] = v;
+        }
+        if (valid && k >= c0 && k < c0 + WIN)
+            for (int r = 0; r < ns; r++) colH += L.H[r] * L.JC[r * L.ldj + (k - c0)];
+        __syncthreads();
+    }
+    {
+        const double *pk = L.park + lane;
+#pragma unroll
+        for (int j = 1; j < NP; j++) a[j] = pk[j * 64];
+    }
+    f = ff[0];
+    // chain rule from (d wdot/dC, d wdot/dT) to J = df/dy (as in jac_prepare)
+    const double T = x.t.T, RT = M.R * T;
+    double resid = 0.0, ra = 0.0, col0 = 0.0, TBk = 0.0, WDk = 0.0, DWTk = 0.0;
+    if (valid) {
+        TBk = L.TB[k];
+        WDk = L.WD[k];
+        DWTk = L.DWT[k];
+        jcc += TBk * x.Ctot;
+        colH *= RT;
+        resid = WDk - jcc;
+        ra = M.W()[k] * x.Wbar * resid / x.rho;
+        col0 = (M.W()[k] / x.rho) * (DWTk + resid * x.t.invT);
+    }
+    const double Hk = RT * x.h[0];
+    const double sumHTB = wsum(valid ? Hk * TBk : 0.0);
+    const double sumHJCC = wsum(valid ? Hk * jcc : 0.0);
+    const double dQT = wsum(valid ? M.R * x.cp[0] * WDk + Hk * (DWTk - jcc * x.t.invT) : 0.0);
+    const double sdcp = wsum(valid ? y * M.R * x.dcp[0] * M.invW()[k] : 0.0);
+    const double fT = bcast(f, 0);
+    const double D = x.rho * x.cpm;
+    if (valid) {
+        const double dQ = M.invW()[k] * (x.rho * (colH + sumHTB) - x.Wbar * sumHJCC);
+        const double dD = x.rho * M.invW()[k] * (M.R * x.cp[0] - x.cpm * x.Wbar);
+        L.TROW[k] = -(dQ + fT * dD) / D;
+    }
+    const double J00 = -(dQT + fT * (-x.rho * x.cpm * x.t.invT + x.rho * sdcp)) / D;
+    __syncthreads();
+    const double alpha = valid ? M.W()[k] : 0.0;
+    const double beta = valid ? M.W()[k] * TBk + ra : 0.0;
+    a[0] = (lane == 0 ? dg : 0.0) - (lane == 0 ? J00 : col0);
+#pragma unroll
+    for (int j = 1; j < NP; j++) {
+        const double Jv = lane == 0 ? L.TROW[j - 1] : L.IW[j - 1] * (alpha * a[j] + beta);
+        a[j] = (lane == j ? dg : 0.0) - Jv;
+    }
+    __syncthreads();
+}
+
 // (J x) for x distributed one component per lane, from the Jacobian pieces in LDS.
-__device__ double jac_times(const DevMech &M, const Lds &L, const JRow &r, double x) {
+__device__ __forceinline__ double jac_times(const DevMech &M, const Lds &L, const JRow &r, double x) {
     const int lane = lane_fresh();
     const int ns = M.nsp;
     const bool sp = lane >= 1 && lane <= ns;
@@ -345,7 +445,7 @@ struct LU {
 };
 
 template <int NP>
-__device__ void lu_factor(double (&a)[NP], LU<NP> &f) {
+__device__ __forceinline__ void lu_factor(double (&a)[NP], LU<NP> &f) {
     const int lane = lane_id();
     bool done = false;
     f.ord = NP;
@@ -374,7 +474,7 @@ __device__ void lu_factor(double (&a)[NP], LU<NP> &f) {
 
 // Solve (L U) x = P b; b and x distributed one component per lane.
 template <int NP>
-__device__ double lu_solve(const double (&a)[NP], const LU<NP> &f, double b) {
+__device__ __forceinline__ double lu_solve(const double (&a)[NP], const LU<NP> &f, double b) {
     const int lane = lane_fresh();
     const int pivv = opaque(f.pivv);
     const int ord = opaque(f.ord);
@@ -396,25 +496,56 @@ __device__ double lu_solve(const double (&a)[NP], const LU<NP> &f, double b) {
 // ---------------------------------------------------------------------------------------
 // one steps
 // ---------------------------------------------------------------------------------------
+// Window count and width of the staged d wdot/dC for a padded size NP, and whether the LU
+// rows are parked in the workspace while the stage right-hand sides are evaluated (so the
+// source-term code does not share the register file with them).
+template <int NP>
+struct WaveShape {
+    static constexpr int NWIN = NP > 32 ? 2 : 1;
+    static constexpr int WIN = NWIN == 1 ? 0 : (NP - 1 + NWIN - 1) / NWIN;   // 0: all ns columns
+    static constexpr bool PARK = NP > 32;
+};
+
+template <int NP>
+__device__ __forceinline__ void park_rows(const Lds &L, const double (&a)[NP]) {
+    double *r = L.park + lane_id();
+#pragma unroll
+    for (int j = 0; j < NP; j++) r[j * 64] = a[j];
+}
+template <int NP>
+__device__ __forceinline__ void unpark_rows(const Lds &L, double (&a)[NP]) {
+    const double *r = L.park + lane_id();
+#pragma unroll
+    for (int j = 0; j < NP; j++) a[j] = r[j * 64];
+}
+
 template <int NP>
 struct Ros4Wave {
+    using SH = WaveShape<NP>;
     static constexpr double qinv = 0.25;
-    __device__ static bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
                                 double &e) {
         double a[NP];
         double f;
-        JRow jr;
         const double dg = 1.0 / (Ros4::gamma * h);
-        jac_rows<NP, double>(M, L, y, P, dg, a, f, jr);
+        if (SH::NWIN == 1) {
+            JRow jr;
+            jac_rows<NP, double>(M, L, y, P, dg, a, f, jr);
+        } else {
+            jac_rows_win<NP, SH::NWIN, SH::WIN>(M, L, y, P, dg, a, f);
+        }
         LU<NP> lu;
         lu_factor<NP>(a, lu);
         const double ih = 1.0 / h;
         const double u1 = lu_solve<NP>(a, lu, f);
+        if (SH::PARK) park_rows<NP>(L, a);
         double yt[1] = {y + Ros4::a21 * u1}, ft[1];
         rhs_wave<1>(M, L, yt, P, ft);
+        if (SH::PARK) unpark_rows<NP>(L, a);
         const double u2 = lu_solve<NP>(a, lu, ft[0] + (Ros4::c21 * u1) * ih);
         yt[0] = y + Ros4::a31 * u1 + Ros4::a32 * u2;
         rhs_wave<1>(M, L, yt, P, ft);
+        if (SH::PARK) unpark_rows<NP>(L, a);
         const double u3 = lu_solve<NP>(a, lu, ft[0] + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
         const double u4 = lu_solve<NP>(a, lu, ft[0] + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
         ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
@@ -441,7 +572,7 @@ struct LU32 {
 };
 
 template <int NP>
-__device__ void lu_factor32(float (&a)[NP], LU32<NP> &f) {
+__device__ __forceinline__ void lu_factor32(float (&a)[NP], LU32<NP> &f) {
     const int lane = lane_id();
     bool done = false;
     f.ord = NP;
@@ -469,7 +600,7 @@ __device__ void lu_factor32(float (&a)[NP], LU32<NP> &f) {
 }
 
 template <int NP>
-__device__ float lu_solve32(const float (&a)[NP], const LU32<NP> &f, float b) {
+__device__ __forceinline__ float lu_solve32(const float (&a)[NP], const LU32<NP> &f, float b) {
     const int lane = lane_fresh();
     const int pivv = opaque(f.pivv);
     const int ord = opaque(f.ord);
@@ -495,7 +626,7 @@ __device__ float lu_solve32(const float (&a)[NP], const LU32<NP> &f, float b) {
 // better conditioned).  With zero sweeps the FP32 solutions are used as they are.
 template <int NP>
 struct Ros4Wave32 {
-    __device__ static bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
                                 double &e, int sweeps) {
         float a[NP];
         double f;
@@ -538,13 +669,13 @@ struct Ros4Wave32 {
 template <int RPL>
 struct Rkf45Wave {
     static constexpr double qinv = 0.2;
-    __device__ static void stage(const DevMech &M, const Lds &L, const double (&yt)[RPL], double P, double h,
+    __device__ static __forceinline__ void stage(const DevMech &M, const Lds &L, const double (&yt)[RPL], double P, double h,
                                  double (&k)[RPL]) {
         rhs_wave<RPL>(M, L, yt, P, k);
 #pragma unroll
         for (int c = 0; c < RPL; c++) k[c] *= h;
     }
-    __device__ static bool step(const DevMech &M, const Lds &L, const double (&y)[RPL], double P, double h,
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, const double (&y)[RPL], double P, double h,
                                 double (&ynew)[RPL], double (&e)[RPL]) {
         double k1[RPL], k2[RPL], k3[RPL], k4[RPL], k5[RPL], k6[RPL], yt[RPL];
         stage(M, L, y, P, h, k1);
@@ -579,7 +710,7 @@ struct Rkf45Wave {
 // per-reactor driver (Algorithm 1 on one wavefront)
 // ---------------------------------------------------------------------------------------
 template <int RPL>
-__device__ double wrms_wave(int N, const double (&e)[RPL], const double (&a)[RPL], const double (&b)[RPL],
+__device__ __forceinline__ double wrms_wave(int N, const double (&e)[RPL], const double (&a)[RPL], const double (&b)[RPL],
                             double rtol, double atol) {
     double s = 0.0;
 #pragma unroll
@@ -595,7 +726,7 @@ __device__ double wrms_wave(int N, const double (&e)[RPL], const double (&a)[RPL
 }
 
 template <int RPL>
-__device__ bool all_finite(int N, const double (&v)[RPL]) {
+__device__ __forceinline__ bool all_finite(int N, const double (&v)[RPL]) {
     bool ok = true;
 #pragma unroll
     for (int c = 0; c < RPL; c++) ok = ok && (lane_id() + 64 * c >= N || isfinite(v[c]));
@@ -606,8 +737,13 @@ __device__ bool all_finite(int N, const double (&v)[RPL]) {
 template <int NP>
 struct Ros4Adapter {
     static constexpr int RPL = 1;
+    static constexpr int NSMAX = NP - 1;
+    static constexpr bool JAC = true;
+    static constexpr int WIN = WaveShape<NP>::WIN;
+    static constexpr bool PARK = WaveShape<NP>::PARK;
+    static constexpr int PARK_ROWS = NP;
     static constexpr double qinv = 0.25;
-    __device__ static bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P, double h,
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P, double h,
                                 double (&yn)[1], double (&e)[1], const IntOpts &) {
         return Ros4Wave<NP>::step(M, L, y[0], P, h, yn[0], e[0]);
     }
@@ -616,15 +752,20 @@ struct Ros4Adapter {
 template <int NP>
 struct Ros4Adapter32 {
     static constexpr int RPL = 1;
+    static constexpr int NSMAX = NP - 1;
+    static constexpr bool JAC = true;
+    static constexpr int WIN = 0;
+    static constexpr bool PARK = false;
+    static constexpr int PARK_ROWS = 0;
     static constexpr double qinv = 0.25;
-    __device__ static bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P, double h,
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P, double h,
                                 double (&yn)[1], double (&e)[1], const IntOpts &o) {
         return Ros4Wave32<NP>::step(M, L, y[0], P, h, yn[0], e[0], o.refine_sweeps);
     }
 };
 
 template <class S>
-__device__ void integrate_reactor(const DevMech &M, const Lds &L, int64_t r, double *y, int64_t ld, const double *p,
+__device__ __forceinline__ void integrate_reactor(const DevMech &M, const Lds &L, int64_t r, double *y, int64_t ld, const double *p,
                                   const double *t_end, double *t_io, double *h_io, const IntOpts &o, int32_t *status,
                                   int32_t *nacc, int32_t *nrej) {
     constexpr int RPL = S::RPL;
@@ -743,8 +884,13 @@ __device__ void integrate_reactor(const DevMech &M, const Lds &L, int64_t r, dou
 template <int R>
 struct Rkf45S {
     static constexpr int RPL = R;
+    static constexpr int NSMAX = 64 * R - 1;
+    static constexpr bool JAC = false;
+    static constexpr int WIN = 0;
+    static constexpr bool PARK = false;
+    static constexpr int PARK_ROWS = 0;
     static constexpr double qinv = 0.2;
-    __device__ static bool step(const DevMech &M, const Lds &L, const double (&y)[R], double P, double h,
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, const double (&y)[R], double P, double h,
                                 double (&yn)[R], double (&e)[R], const IntOpts &) {
         return Rkf45Wave<R>::step(M, L, y, P, h, yn, e);
     }
@@ -815,9 +961,13 @@ template <class S>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) integrate_wave_kernel(DevMech M, int64_t n, double *y, int64_t ld,
                                                             const double *p, const double *t_end, double *t_io,
                                                             double *h_io, IntOpts o, unsigned *queue,
-                                                            int32_t *status, int32_t *nacc, int32_t *nrej, bool jac) {
+                                                            double *park, int32_t *status, int32_t *nacc,
+                                                            int32_t *nrej) {
+    // LDS laid out for the largest species count of the instantiation: every offset is a
+    // compile-time constant, so LDS addresses need no scalar registers
     extern __shared__ double lds_raw[];
-    const Lds L = carve(lds_raw, M.nsp, jac);
+    Lds L = carve(lds_raw, S::NSMAX, S::JAC, S::WIN > 0 ? S::WIN : S::NSMAX);
+    if (S::PARK) L.park = park + size_t(blockIdx.x) * (size_t(S::PARK_ROWS) * 64);
     init_lds(M, L);
     for (;;) {
         unsigned v = 0;
@@ -837,22 +987,28 @@ __global__ void zero_u32_kernel(unsigned *q) { *q = 0u; }
 namespace {
 int pad_np(int N) { return ((N + 7) / 8) * 8; }
 
+// Resident wavefronts per CU are capped so that parked LU rows fit the workspace.
+constexpr int kWaveMaxPerCu = 8;
+
 template <class S>
 int launch_int(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end, double *t,
-               double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc, int32_t *nrej, bool jac,
+               double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc, int32_t *nrej,
                hipStream_t s) {
-    const size_t lds = lds_doubles(M.nsp, jac) * sizeof(double);
+    if (M.nsp > S::NSMAX) return CK_EUNSUPPORTED;
+    const size_t lds = lds_doubles(S::NSMAX, S::JAC, S::WIN > 0 ? S::WIN : S::NSMAX) * sizeof(double);
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return CK_EHIP;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return CK_EHIP;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, integrate_wave_kernel<S>, 64, lds) != hipSuccess || per < 1)
         return CK_EHIP;
     if (o.blocks_per_cu > 0 && o.blocks_per_cu < per) per = o.blocks_per_cu;
+    if (per > kWaveMaxPerCu) per = kWaveMaxPerCu;
     int64_t grid = int64_t(cus) * per;
     if (grid > n) grid = n;
+    double *park = S::PARK ? reinterpret_cast<double *>(reinterpret_cast<char *>(queue) + 256) : nullptr;
     zero_u32_kernel<<<1, 1, 0, s>>>(queue);
     integrate_wave_kernel<S><<<dim3(unsigned(grid)), dim3(64), lds, s>>>(M, n, y, ld, p, t_end, t, h, o, queue,
-                                                                          status, nacc, nrej, jac);
+                                                                          park, status, nacc, nrej);
     return hipGetLastError() == hipSuccess ? CK_OK : CK_EHIP;
 }
 }  // namespace
@@ -862,7 +1018,12 @@ bool wave_supported(const DevMech &M, int method, int precision) {
     return precision == CK_PREC_FP64 && M.N <= 128;
 }
 
-size_t wave_ws_bytes(const DevMech &, int64_t) { return 256; }
+size_t wave_ws_bytes(const DevMech &M, int cus) {
+    // parked FP64 LU rows of every resident wavefront (FP64 ROS4 with 32 < NP <= 64)
+    const int np = pad_np(M.N);
+    if (np <= 32 || np > 64) return 256;
+    return 256 + size_t(cus) * kWaveMaxPerCu * size_t(np) * 64 * sizeof(double);
+}
 
 int launch_rhs_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
                     hipStream_t s) {
@@ -889,13 +1050,13 @@ int launch_integrate_wave(int method, const DevMech &M, int64_t n, double *y, in
                           int32_t *nacc, int32_t *nrej, hipStream_t s) {
     unsigned *q = static_cast<unsigned *>(ws);
     if (method == 1) {
-        if (M.N <= 64) return launch_int<Rkf45S<1>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, false, s);
-        return launch_int<Rkf45S<2>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, false, s);
+        if (M.N <= 64) return launch_int<Rkf45S<1>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+        return launch_int<Rkf45S<2>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
     }
     if (o.precision == CK_PREC_FP32_REFINE) {
         switch (pad_np(M.N)) {
 #define CK_CASE32(NPV) \
-    case NPV: return launch_int<Ros4Adapter32<NPV>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);
+    case NPV: return launch_int<Ros4Adapter32<NPV>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
             CK_CASE32(8) CK_CASE32(16) CK_CASE32(24) CK_CASE32(32) CK_CASE32(40) CK_CASE32(48) CK_CASE32(56)
             CK_CASE32(64)
 #undef CK_CASE32
@@ -903,14 +1064,14 @@ int launch_integrate_wave(int method, const DevMech &M, int64_t n, double *y, in
         }
     }
     switch (pad_np(M.N)) {
-        case 8: return launch_int<Ros4Adapter<8>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);
-        case 16: return launch_int<Ros4Adapter<16>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);
-        case 24: return launch_int<Ros4Adapter<24>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);
-        case 32: return launch_int<Ros4Adapter<32>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);
-        case 40: return launch_int<Ros4Adapter<40>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);
-        case 48: return launch_int<Ros4Adapter<48>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);
-        case 56: return launch_int<Ros4Adapter<56>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);
-        case 64: return launch_int<Ros4Adapter<64>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, true, s);
+        case 8: return launch_int<Ros4Adapter<8>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+        case 16: return launch_int<Ros4Adapter<16>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+        case 24: return launch_int<Ros4Adapter<24>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+        case 32: return launch_int<Ros4Adapter<32>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+        case 40: return launch_int<Ros4Adapter<40>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+        case 48: return launch_int<Ros4Adapter<48>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+        case 56: return launch_int<Ros4Adapter<56>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+        case 64: return launch_int<Ros4Adapter<64>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
         default: return CK_EUNSUPPORTED;
     }
 }

@@ -24,7 +24,7 @@ int launch_integrate_lane(int method, const DevMech &M, int64_t n, double *y, in
 
 // wavefront-per-reactor family (k_wave.hip)
 bool wave_supported(const DevMech &M, int method, int precision);
-size_t wave_ws_bytes(const DevMech &M, int64_t n);
+size_t wave_ws_bytes(const DevMech &M, int cus);   // queue counter + parked LU rows
 int launch_rhs_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
                     hipStream_t s);
 int launch_jac_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
