@@ -105,6 +105,9 @@ def parse():
     ap.add_argument("--rhs-batches", type=int, default=8, help="distinct state batches cycled in the RHS leg")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 8 per host core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--suite", default="integrate", choices=["integrate", "batching", "precision", "serving"],
+                    help="integrate: the headline line; batching / precision / serving: the three production "
+                         "forms (one JSON line each, bounded workloads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (counter calibration) and exit")
     return ap.parse_args()
@@ -126,6 +129,116 @@ def cpu_baseline(path, y, P, t_end, sample):
                 mean_steps=float(np.mean(res["n_accept"] + res["n_reject"])))
 
 
+def _states(synth, torch, mech, n, seed):
+    recipe = {"M13": "small", "M53": "mid", "M111": "divergent"}[mech]
+    y0, P = synth.reactor_states({"M13": 13, "M53": 53, "M111": 111}[mech], n, recipe, seed=seed)
+    dev = torch.device("cuda", 0)
+    return torch.as_tensor(y0, device=dev), torch.as_tensor(P, device=dev)
+
+
+def _timed_integrate(ck, torch, g, y, P, t_end, **opts):
+    """One integrate call on a copy of y; returns (result, seconds) with HIP events on the current stream."""
+    yy = y.clone()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    r = ck.integrate(g, yy, P, t_end, inplace=True, **opts)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return r, e0.elapsed_time(e1) / 1e3
+
+
+def suite_batching(a):
+    """Batching against divergence (111 species, 262144 reactors, half near ignition and half cold):
+    the persistent work-queue workgroup kernel against the plain one-reactor-per-lane kernel, each
+    given the same number of attempted steps per reactor; and the waste the lane kernel would incur,
+    from the step counts of a sample integrated to completion."""
+    import torch
+
+    from paper_1608_05794_amd import ck, metrics, synth
+    out = {"suite": "batching", "unit": "reactor-steps/s", "data": "synthetic", "dtype": "f64"}
+    for mech, n, steps, kernels in (("M111", 262144, 24, ("group", "lane")), ("M53", 131072, 60, ("wave", "lane"))):
+        g = ck.Mechanism(synth.mechanism_file(mech))
+        y, P = _states(synth, torch, mech, n, {"M53": 1002, "M111": 1003}[mech])
+        row = {}
+        for k in kernels:
+            r, dt = _timed_integrate(ck, torch, g, y, P, 1e-3, kernel=k, max_steps=steps)
+            done = float((r["n_accept"] + r["n_reject"]).sum().item())
+            row[k] = {"reactor_steps_per_s": done / dt, "seconds": dt}
+            print(f"batching {mech} {k}: {done / dt / 1e6:.3f} M reactor-steps/s", file=sys.stderr, flush=True)
+        row["speedup"] = row[kernels[0]]["reactor_steps_per_s"] / row[kernels[1]]["reactor_steps_per_s"]
+        out[f"{mech}_x{n}_{steps}_steps"] = row
+    # waste of lockstep groups (Eq. waste) from complete integrations of a 111-species sample
+    g = ck.Mechanism(synth.mechanism_file("M111"))
+    y, P = _states(synth, torch, "M111", 2048, 1003)
+    r, dt = _timed_integrate(ck, torch, g, y, P, 1e-9, kernel="group")
+    st = (r["n_accept"] + r["n_reject"]).cpu().numpy()
+    out["waste_sample"] = {
+        "reactors": 2048, "t_end": 1e-9, "mean_steps": float(st.mean()), "max_steps": int(st.max()),
+        "mean_waste_by_width": {w: float(metrics.waste(st, w).mean()) for w in (4, 8, 16, 32, 64)},
+        "lane_efficiency_64": metrics.lane_efficiency(st, 64),
+        "waste_cdf": {str(w): v for w, v in metrics.waste_cdf(st).items()}}
+    return out
+
+
+def suite_precision(a):
+    """FP32 LU with FP64 refinement against the all-FP64 solver (53 species): step counts and the
+    largest relative differences of T and Y (Y > 1e-12) over the whole batch, and throughput."""
+    import torch
+
+    from paper_1608_05794_amd import ck, synth
+    n, te = 16384, 1e-5
+    g = ck.Mechanism(synth.mechanism_file("M53"))
+    y, P = _states(synth, torch, "M53", n, 1002)
+    res = {}
+    for prec in ("fp64", "fp32_refine"):
+        r, dt = _timed_integrate(ck, torch, g, y, P, te, kernel="wave", precision=prec)
+        res[prec] = (r, dt)
+        print(f"precision {prec}: {dt:.1f} s", file=sys.stderr, flush=True)
+    r64, r32 = res["fp64"][0], res["fp32_refine"][0]
+    T64, T32 = r64["y"][0], r32["y"][0]
+    Y64, Y32 = r64["y"][1:], r32["y"][1:]
+    mask = Y64.abs() > 1e-12
+    relY = ((Y32 - Y64).abs() / Y64.abs().clamp_min(1e-300))[mask]
+    out = {"suite": "precision", "workload": f"M53 x {n} reactors, ROS4 to {te:g} s, rtol 1e-8, atol 1e-12",
+           "data": "synthetic"}
+    for prec, (r, dt) in res.items():
+        na, nr = int(r["n_accept"].sum().item()), int(r["n_reject"].sum().item())
+        out[prec] = {"accepted": na, "rejected": nr, "seconds": dt, "reactor_steps_per_s": (na + nr) / dt,
+                     "status_ok": int((r["status"] == 0).sum().item())}
+    out["fp32_vs_fp64"] = {"max_rel_T": float(((T32 - T64).abs() / T64).max().item()),
+                           "max_rel_Y_above_1e-12": float(relY.max().item()),
+                           "median_rel_Y_above_1e-12": float(relY.median().item()),
+                           "identical_step_counts": float(((r64["n_accept"] + r64["n_reject"]) ==
+                                                           (r32["n_accept"] + r32["n_reject"])).float().mean())}
+    return out
+
+
+def suite_serving(a):
+    """Continuous batching: a Poisson request stream (2000 requests/s offered; mechanisms 13 / 53 / 111
+    species with weights 0.3 / 0.5 / 0.2; reactor count and end time log-uniform) served under a 200 GB
+    HBM budget; completed-request latency p50 / p99 and throughput.  Bounded: 64 requests with at most
+    2048 reactors and end times 1e-8 to 1e-6 s."""
+    import torch
+
+    from paper_1608_05794_amd import ck, serve, synth
+    mechs = {m: ck.Mechanism(synth.mechanism_file(m)) for m in ("M13", "M53", "M111")}
+    species = {m: g.n_species for m, g in mechs.items()}
+    reqs = serve.poisson_requests(64, 2000.0, seed=5000, n_range=(1, 2048), t_range=(1e-8, 1e-6), species=species)
+    srv = serve.Server(mechs, capacity={"M13": 16384, "M53": 16384, "M111": 8192}, hbm_budget=200e9,
+                       launch_steps=400)
+    t0 = time.perf_counter()
+    done = srv.run(reqs, time_limit=240.0, log=lambda m: print(m, file=sys.stderr, flush=True))
+    el = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    summ = serve.latency_summary(done, 2000.0, el)
+    return {"suite": "serving", "requests": len(reqs), "completed": len(done), "elapsed_s": el,
+            "iterations": srv.iterations, "reactors": sum(r.n for r in reqs), **summ,
+            "stream": "64 requests, Poisson 2000/s, mechanisms 0.3/0.5/0.2, reactors log-uniform 1-2048, "
+                      "t_end log-uniform 1e-8-1e-6 s, 200 GB budget"}
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -133,6 +246,11 @@ def main():
               "MI355X; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if a.suite != "integrate":
+        fn = {"batching": suite_batching, "precision": suite_precision, "serving": suite_serving}[a.suite]
+        print(json.dumps(fn(a)), flush=True)
+        return
 
     if a.copy_calibration:
         n = a.copy_calibration * (1 << 20) // 8

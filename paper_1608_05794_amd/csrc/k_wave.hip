@@ -508,13 +508,13 @@ struct WaveShape {
 
 template <int NP>
 __device__ __forceinline__ void park_rows(const Lds &L, const double (&a)[NP]) {
-    double *r = L.park + lane_id();
+    double *r = L.park + lane_fresh();
 #pragma unroll
     for (int j = 0; j < NP; j++) r[j * 64] = a[j];
 }
 template <int NP>
 __device__ __forceinline__ void unpark_rows(const Lds &L, double (&a)[NP]) {
-    const double *r = L.park + lane_id();
+    const double *r = L.park + lane_fresh();
 #pragma unroll
     for (int j = 0; j < NP; j++) a[j] = r[j * 64];
 }
