@@ -25,7 +25,21 @@ sys.path.insert(0, ROOT)
 METRIC = "reactors/s integrated (ROS4, rtol 1e-8), RHS evals/s, p50/p99 solve latency"
 KERNEL_NAMES = {"wave": "integrate_wave_kernel<Ros4Adapter>", "auto": "integrate_wave_kernel<Ros4Adapter>",
                 "group": "coop_kernel<Ros4Coop>", "lane": "integrate_lane_kernel<0>"}
-PEAK_FP64_VECTOR = 78.6e12          # FLOP/s, MI355X FP64 vector (VALU)
+PEAK_FP64_VECTOR = 78.6e12
+# HBM traffic of the integrator kernel from two rocprofv3 --pmc runs of the default command (one
+# with FETCH_SIZE, one with WRITE_SIZE; KiB per dispatch averaged over its launches), each scaled
+# by what the counter reads for a device-to-device copy of 1 GiB (FETCH_SIZE reads half the bytes,
+# WRITE_SIZE all of them).  Valid only for the default workload and for kernel sources whose hash
+# matches; otherwise the traffic is reported as null.
+TRAFFIC_REF = {
+    "sources": ["paper_1608_05794_amd/csrc/k_wave.hip", "paper_1608_05794_amd/csrc/kinetics.h",
+                "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h"],
+    "sha256": "af2a157932cedf005fb67ade32453b93340c46a19849a508dc3c0713fadc7bc4",
+    "args": {"mech": "M53", "reactors": 131072, "t_end": 1e-3, "kernel": "wave", "precision": "fp64",
+             "launch_steps": 2000},
+    "fetch_kib_per_launch": 3772271907.0, "fetch_factor": 1048576.0 / 524302.3,
+    "write_kib_per_launch": 5489005747.5, "write_factor": 1.0,
+}          # FLOP/s, MI355X FP64 vector (VALU)
 TRANSCENDENTAL_FLOPS = 20           # FP64 operations charged per exp / log / log10 / exp10
 
 
@@ -111,6 +125,22 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (counter calibration) and exit")
     return ap.parse_args()
+
+
+def measured_traffic(a):
+    """HBM bytes per launch of the integrator kernel (see TRAFFIC_REF), or None."""
+    import hashlib
+    ref = TRAFFIC_REF
+    if any(getattr(a, k) != v for k, v in ref["args"].items()):
+        return None
+    digests = []
+    for f in ref["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            digests.append(hashlib.sha256(fh.read()).hexdigest())
+    if hashlib.sha256("".join(digests).encode()).hexdigest() != ref["sha256"]:
+        return None
+    return (ref["fetch_kib_per_launch"] * 1024 * ref["fetch_factor"] +
+            ref["write_kib_per_launch"] * 1024 * ref["write_factor"])
 
 
 def cpu_baseline(path, y, P, t_end, sample):
@@ -364,7 +394,8 @@ def main():
         "launches_per_step": launches,
         "status_counts": {"ok": status[0], "max_steps": status[1], "h_underflow": status[2], "nonfinite": status[3]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": measured_traffic(a),
+                     "traffic_unit": "bytes per launch",
                      "kernel": KERNEL_NAMES[a.kernel].replace("Adapter", "Adapter32" if a.precision != "fp64" else "Adapter"),
                      "launches": launches,
                      "avg_launch_ms": 1e3 * kernel_s / launches,

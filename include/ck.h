@@ -59,6 +59,14 @@ enum {
                               wavefronts, persistent work queue, Gauss-Jordan inverse in registers */
 };
 
+/* Jacobian used by ROS4. */
+enum {
+    CK_JAC_ANALYTIC = 0,   /* analytic Jacobian (chain rule through the rates of progress) */
+    CK_JAC_FD = 1          /* forward differences, one source-term evaluation per column (the
+                              paper's set-up, Section 5; increments as CVODE's dense difference
+                              quotient); wavefront kernel, FP64, N <= 64 */
+};
+
 /* Precision of the Rosenbrock linear solves. */
 enum {
     CK_PREC_FP64 = 0,      /* FP64 LU and triangular solves */
@@ -76,10 +84,12 @@ typedef struct {
     int32_t refine_sweeps; /* FP32 mode: maximum FP64 refinement sweeps, 0..3 */
     int32_t blocks_per_cu; /* persistent kernels (WAVE, GROUP): resident workgroups per compute unit;
                               0 = as many as registers and LDS allow (larger values are clamped) */
+    int32_t jacobian;      /* CK_JAC_* (ROS4 only) */
+    int32_t reserved;      /* must be 0 */
 } ck_opts;
 
 /* Fills *o with the defaults: rtol 1e-8, atol 1e-12, h0 0, h_fixed 0, max_steps 1e6,
- * CK_KERNEL_AUTO, CK_PREC_FP64, refine_sweeps 3, blocks_per_cu 0. */
+ * CK_KERNEL_AUTO, CK_PREC_FP64, refine_sweeps 3, blocks_per_cu 0, CK_JAC_ANALYTIC. */
 void ck_opts_default(ck_opts *o);
 
 const char *ck_strerror(int code);

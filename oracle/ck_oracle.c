@@ -499,6 +499,8 @@ typedef struct {
     orc_work *w;
     const double *A;          /* linear system if m == NULL */
     long nfev, njev;
+    int jac_fd;               /* ROS4 Jacobian: 0 analytic, 1 forward differences */
+    double rtol, atol;        /* error weights of the difference increments */
 } orc_problem;
 
 static void prob_f(orc_problem *p, const double *y, double *f)
@@ -525,6 +527,39 @@ static void prob_jac(orc_problem *p, const double *y, double *J)
         return;
     }
     memcpy(J, p->A, sizeof(double) * p->N * p->N);
+}
+
+/* Forward-difference Jacobian, one extra source-term evaluation per column (the
+ * paper's ROS4 set-up, Section 5: first-order forward differences as in
+ * CVODE's dense difference-quotient Jacobian).  Increment of column j:
+ *   inc_j = max(sqrt(eps) |y_j|, min_inc / w_j),  w_j = 1 / (rtol |y_j| + atol),
+ *   min_inc = 1000 |h| eps N ||f(y)||_w  (1 if that norm is 0),
+ * ||.||_w the weighted RMS norm with the weights w; J_ij = (f_i(y + inc_j e_j) - f_i(y)) / inc_j. */
+static void jacobian_fd(orc_problem *p, const double *y, double h, double *J)
+{
+    const int N = p->N;
+    const double eps = 2.220446049250313e-16;
+    double *f0 = malloc(sizeof(double) * N), *f1 = malloc(sizeof(double) * N);
+    double *yp = malloc(sizeof(double) * N);
+    p->njev++;
+    prob_f(p, y, f0);
+    double s = 0.0;
+    for (int i = 0; i < N; i++) {
+        double r = f0[i] / (p->rtol * fabs(y[i]) + p->atol);
+        s += r * r;
+    }
+    const double fnorm = sqrt(s / N);
+    const double min_inc = (fnorm != 0.0) ? 1000.0 * fabs(h) * eps * N * fnorm : 1.0;
+    memcpy(yp, y, sizeof(double) * N);
+    for (int j = 0; j < N; j++) {
+        const double wj = 1.0 / (p->rtol * fabs(y[j]) + p->atol);
+        const double inc = fmax(sqrt(eps) * fabs(y[j]), min_inc / wj);
+        yp[j] = y[j] + inc;
+        prob_f(p, yp, f1);
+        for (int i = 0; i < N; i++) J[i * N + j] = (f1[i] - f0[i]) / inc;
+        yp[j] = y[j];
+    }
+    free(f0); free(f1); free(yp);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -619,7 +654,10 @@ static int ros4_step(orc_problem *p, step_work *sw, const double *y, double h, d
 {
     const int N = p->N;
     double *u = sw->u, *M = sw->M, *ytmp = sw->ytmp, *f = sw->f;
-    prob_jac(p, y, M);
+    if (p->jac_fd)
+        jacobian_fd(p, y, h, M);
+    else
+        prob_jac(p, y, M);
     for (int i = 0; i < N * N; i++) M[i] = -M[i];
     for (int i = 0; i < N; i++) M[i * N + i] += 1.0 / (ROS_GAMMA * h);
     int info = lu_factor(N, M, sw->piv);
@@ -687,6 +725,8 @@ typedef struct {
     double h0;          /* > 0: initial step given */
     double h_fixed;     /* > 0: fixed-step mode, every step accepted */
     int64_t max_steps;  /* attempted steps */
+    int32_t jac_fd;     /* ROS4 Jacobian: 0 analytic, 1 forward differences */
+    int32_t pad;
 } orc_opts;
 
 enum { ST_OK = 0, ST_MAX_STEPS = 1, ST_H_UNDERFLOW = 2, ST_NONFINITE = 3 };
@@ -734,6 +774,9 @@ static int integrate_one(orc_problem *p, int method, double *y, double *t_io, do
 {
     const int N = p->N;
     const double q = (method == 0) ? 4.0 : 5.0;   /* error estimate is O(h^q) */
+    p->jac_fd = o->jac_fd;
+    p->rtol = o->rtol;
+    p->atol = o->atol;
     step_work sw;
     sw.ytmp = malloc(sizeof(double) * N);
     sw.f = malloc(sizeof(double) * N);
@@ -852,6 +895,26 @@ void orc_jac(const orc_mech *m, int64_t n, const double *y, const double *P, dou
 
 /* Forward and reverse gross rates of progress q_f = c kf prod C^nu', q_r = c kr prod C^nu''
  * (per reaction) and the thermo of one state; used by the tests' scaled error metric. */
+/* Forward-difference Jacobian of each reactor (AoS, as orc_jac), increments for step h and
+ * tolerances rtol / atol (see jacobian_fd). */
+void orc_jac_fd(const orc_mech *m, int64_t n, const double *y, const double *P, double rtol, double atol,
+                double h, double *jac, int nthreads)
+{
+    const int N = m->nsp + 1;
+    set_threads(nthreads);
+#pragma omp parallel
+    {
+        orc_work w;
+        work_init(m, &w);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t r = 0; r < n; r++) {
+            orc_problem p = {N, m, P[r], &w, NULL, 0, 0, 1, rtol, atol};
+            jacobian_fd(&p, y + r * N, h, jac + r * N * N);
+        }
+        work_free(&w);
+    }
+}
+
 void orc_rates(const orc_mech *m, const double *y, double P, double *qf, double *qr, double *rho, double *cp_mass, double *h_RT)
 {
     orc_work w;
@@ -887,7 +950,7 @@ int orc_integrate(const orc_mech *m, int method, int64_t n, double *y, const dou
         work_init(m, &w);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t r = 0; r < n; r++) {
-            orc_problem p = {N, m, P[r], &w, NULL, 0, 0};
+            orc_problem p = {N, m, P[r], &w, NULL, 0, 0, 0, 0.0, 0.0};
             status[r] = integrate_one(&p, method, y + r * N, t ? t + r : NULL, h ? h + r : NULL, t_end[r], o,
                                       nacc + r, nrej + r);
         }
@@ -900,7 +963,7 @@ int orc_integrate(const orc_mech *m, int method, int64_t n, double *y, const dou
 int orc_integrate_linear(int method, int N, const double *A, double *y, double t_end, double *t, double *h,
                          const orc_opts *o, int32_t *status, int32_t *nacc, int32_t *nrej, long *nfev)
 {
-    orc_problem p = {N, NULL, 0.0, NULL, A, 0, 0};
+    orc_problem p = {N, NULL, 0.0, NULL, A, 0, 0, 0, 0.0, 0.0};
     *status = integrate_one(&p, method, y, t, h, t_end, o, nacc, nrej);
     if (nfev) *nfev = p.nfev;
     return 0;
@@ -909,7 +972,7 @@ int orc_integrate_linear(int method, int N, const double *A, double *y, double t
 /* One step of either method on y' = A y from y (no control): returns y* and the error vector. */
 int orc_step_linear(int method, int N, const double *A, const double *y, double h, double *ynew, double *err)
 {
-    orc_problem p = {N, NULL, 0.0, NULL, A, 0, 0};
+    orc_problem p = {N, NULL, 0.0, NULL, A, 0, 0, 0, 0.0, 0.0};
     step_work sw;
     sw.ytmp = malloc(sizeof(double) * N);
     sw.f = malloc(sizeof(double) * N);

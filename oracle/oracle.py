@@ -18,7 +18,7 @@ _lib = None
 
 class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double),
-                ("h_fixed", C.c_double), ("max_steps", C.c_int64)]
+                ("h_fixed", C.c_double), ("max_steps", C.c_int64), ("jac_fd", C.c_int32), ("pad", C.c_int32)]
 
 
 def lib():
@@ -35,6 +35,7 @@ def lib():
         L.orc_thermo.argtypes = [vp, C.c_double, dp, dp, dp]
         L.orc_rhs.argtypes = [vp, i64, dp, dp, dp, C.c_int]
         L.orc_jac.argtypes = [vp, i64, dp, dp, dp, C.c_int]
+        L.orc_jac_fd.argtypes = [vp, i64, dp, dp, C.c_double, C.c_double, C.c_double, dp, C.c_int]
         L.orc_rates.argtypes = [vp, dp, C.c_double, dp, dp, dp, dp, dp]
         L.orc_stoich.argtypes = [vp, C.POINTER(C.c_int)]
         L.orc_integrate.argtypes = [vp, C.c_int, i64, dp, dp, dp, dp, dp, C.POINTER(Opts), ip, ip, ip, C.c_int]
@@ -58,8 +59,11 @@ def _i(a):
 METHODS = {"ros4": 0, "rkf45": 1}
 
 
-def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000):
-    return Opts(rtol, atol, h0, h_fixed, max_steps)
+JACOBIANS = {"analytic": 0, "fd": 1}
+
+
+def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000, jacobian="analytic"):
+    return Opts(rtol, atol, h0, h_fixed, max_steps, JACOBIANS[jacobian], 0)
 
 
 class Mechanism:
@@ -125,8 +129,18 @@ class Mechanism:
         lib().orc_jac(self._h, n, _d(aos), _d(Pa), _d(out), nthreads)
         return out
 
+    def jac_fd(self, y, P, h, rtol=1e-8, atol=1e-12, nthreads=0):
+        """Forward-difference Jacobian (increments for step h and tolerances rtol / atol), as jac()."""
+        y = np.asarray(y, dtype=np.float64)
+        n = y.shape[1]
+        aos = np.array(y.T, dtype=np.float64, order="C", copy=True)
+        out = np.zeros((n, self.N, self.N))
+        Pa = np.ascontiguousarray(P, dtype=np.float64)
+        lib().orc_jac_fd(self._h, n, _d(aos), _d(Pa), float(rtol), float(atol), float(h), _d(out), nthreads)
+        return out
+
     def integrate(self, y, P, t_end, method="ros4", rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0,
-                  max_steps=1_000_000, t=None, h=None, nthreads=0):
+                  max_steps=1_000_000, t=None, h=None, nthreads=0, jacobian="analytic"):
         """Integrate each reactor to t_end.  Returns dict(y, t, h, status, n_accept, n_reject)."""
         y = np.asarray(y, dtype=np.float64)
         n = y.shape[1]
@@ -136,20 +150,21 @@ class Mechanism:
         tt = np.zeros(n) if t is None else np.array(t, dtype=np.float64)
         hh = np.zeros(n) if h is None else np.array(h, dtype=np.float64)
         st, na, nr = (np.zeros(n, dtype=np.int32) for _ in range(3))
-        o = make_opts(rtol, atol, h0, h_fixed, max_steps)
+        o = make_opts(rtol, atol, h0, h_fixed, max_steps, jacobian)
         lib().orc_integrate(self._h, METHODS[method], n, _d(aos), _d(Pa), _d(te), _d(tt), _d(hh), C.byref(o),
                             _i(st), _i(na), _i(nr), nthreads)
         return dict(y=np.ascontiguousarray(aos.T), t=tt, h=hh, status=st, n_accept=na, n_reject=nr)
 
 
-def integrate_linear(A, y0, t_end, method="ros4", rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000):
+def integrate_linear(A, y0, t_end, method="ros4", rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000,
+                     jacobian="analytic"):
     A = np.ascontiguousarray(A, dtype=np.float64)
     N = A.shape[0]
     y = np.array(y0, dtype=np.float64)
     t, h = C.c_double(0.0), C.c_double(0.0)
     st, na, nr = C.c_int32(), C.c_int32(), C.c_int32()
     nfev = C.c_long()
-    o = make_opts(rtol, atol, h0, h_fixed, max_steps)
+    o = make_opts(rtol, atol, h0, h_fixed, max_steps, jacobian)
     lib().orc_integrate_linear(METHODS[method], N, _d(A), _d(y), float(t_end), C.byref(t), C.byref(h), C.byref(o),
                                C.byref(st), C.byref(na), C.byref(nr), C.byref(nfev))
     return dict(y=y, t=t.value, h=h.value, status=st.value, n_accept=na.value, n_reject=nr.value, nfev=nfev.value)

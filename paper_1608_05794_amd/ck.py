@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libck.so")
 
 KERNELS = {"auto": 0, "lane": 1, "wave": 2, "group": 3}
 PRECISIONS = {"fp64": 0, "fp32_refine": 1}
+JACOBIANS = {"analytic": 0, "fd": 1}
 STATUS = {0: "ok", 1: "max_steps", 2: "h_underflow", 3: "nonfinite"}
 
 
@@ -27,7 +28,7 @@ class CkError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double), ("h_fixed", C.c_double),
                 ("max_steps", C.c_int64), ("kernel", C.c_int32), ("precision", C.c_int32),
-                ("refine_sweeps", C.c_int32), ("blocks_per_cu", C.c_int32)]
+                ("refine_sweeps", C.c_int32), ("blocks_per_cu", C.c_int32), ("jacobian", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -87,7 +88,7 @@ def _state(y, N):
 
 
 def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000, kernel="auto", precision="fp64",
-              refine_sweeps=3, blocks_per_cu=0):
+              refine_sweeps=3, blocks_per_cu=0, jacobian="analytic"):
     o = Opts()
     lib().ck_opts_default(C.byref(o))
     o.rtol, o.atol, o.h0, o.h_fixed, o.max_steps = rtol, atol, h0, h_fixed, max_steps
@@ -95,6 +96,7 @@ def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000, k
     o.precision = PRECISIONS[precision]
     o.refine_sweeps = refine_sweeps
     o.blocks_per_cu = blocks_per_cu
+    o.jacobian = JACOBIANS[jacobian]
     return o
 
 

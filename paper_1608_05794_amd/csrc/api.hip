@@ -62,6 +62,8 @@ int validate_opts(const ck_opts *o, IntOpts &io) {
     if (o->precision != CK_PREC_FP64 && o->precision != CK_PREC_FP32_REFINE) return CK_EINVAL;
     if (o->refine_sweeps < 0 || o->refine_sweeps > 3) return CK_EINVAL;
     if (o->blocks_per_cu < 0) return CK_EINVAL;
+    if (o->jacobian != CK_JAC_ANALYTIC && o->jacobian != CK_JAC_FD) return CK_EINVAL;
+    if (o->reserved != 0) return CK_EINVAL;
     io.rtol = o->rtol;
     io.atol = o->atol;
     io.h0 = o->h0;
@@ -70,6 +72,7 @@ int validate_opts(const ck_opts *o, IntOpts &io) {
     io.precision = o->precision;
     io.refine_sweeps = o->refine_sweeps;
     io.blocks_per_cu = o->blocks_per_cu;
+    io.jacobian = o->jacobian;
     return CK_OK;
 }
 
@@ -80,6 +83,12 @@ int choose_kernel(const ck_mech *m, int method, const ck_opts *o) {
     if (!o) o = &d;
     const bool fp64 = o->precision == CK_PREC_FP64;
     const bool wave_ok = wave_supported(m->dev, method, o->precision);
+    if (method == 0 && o->jacobian == CK_JAC_FD) {
+        // forward-difference Jacobian: wavefront kernel, FP64 only
+        if (!fp64 || !wave_ok || (o->kernel != CK_KERNEL_AUTO && o->kernel != CK_KERNEL_WAVE))
+            return CK_EUNSUPPORTED;
+        return CK_KERNEL_WAVE;
+    }
     const bool group_ok = method == 0 && fp64 && coop_supported(m->dev);
     switch (o->kernel) {
         case CK_KERNEL_WAVE: return wave_ok ? CK_KERNEL_WAVE : CK_EUNSUPPORTED;
@@ -140,6 +149,8 @@ extern "C" void ck_opts_default(ck_opts *o) {
     o->precision = CK_PREC_FP64;
     o->refine_sweeps = 3;
     o->blocks_per_cu = 0;
+    o->jacobian = CK_JAC_ANALYTIC;
+    o->reserved = 0;
 }
 
 extern "C" const char *ck_strerror(int code) {

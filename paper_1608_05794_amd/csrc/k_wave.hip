@@ -554,6 +554,63 @@ struct Ros4Wave {
     }
 };
 
+// ROS4 step with a forward-difference Jacobian (the paper's ROS4 set-up, Section 5): column j of
+// J is (f(y + inc_j e_j) - f(y)) / inc_j, one source-term evaluation per column, with
+//   inc_j = max(sqrt(eps) |y_j|, min_inc (rtol |y_j| + atol)),
+//   min_inc = 1000 |h| eps N ||f(y)||_w (1 if that norm is 0), w_i = 1 / (rtol |y_i| + atol),
+// as CVODE's dense difference quotient.  Columns are written to the parking slice (lane i holds
+// row i), then loaded as the lane's row; f(y) doubles as the first stage's right-hand side.
+template <int NP>
+struct Ros4WaveFD {
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h,
+                                                double &ynew, double &e, const IntOpts &o) {
+        constexpr double eps = 2.220446049250313e-16;
+        const int N = M.N;
+        const int lane = lane_fresh();
+        const bool comp = lane < N;
+        double yy[1] = {y}, f0[1];
+        rhs_wave<1>(M, L, yy, P, f0);
+        const double r = comp ? f0[0] / (o.rtol * fabs(y) + o.atol) : 0.0;
+        const double fnorm = sqrt(wsum(r * r) / N);
+        const double min_inc = fnorm != 0.0 ? 1000.0 * fabs(h) * eps * N * fnorm : 1.0;
+        {
+            double *pk = L.park + lane_fresh();
+            for (int j = 0; j < N; j++) {
+                const double yj = bcast(y, j);
+                const double wj = 1.0 / (o.rtol * fabs(yj) + o.atol);
+                const double inc = fmax(sqrt(eps) * fabs(yj), min_inc / wj);
+                double yp[1] = {lane == j ? yj + inc : y}, fj[1];
+                rhs_wave<1>(M, L, yp, P, fj);
+                pk[j * 64] = comp ? (fj[0] - f0[0]) / inc : 0.0;   // J[lane][j]
+            }
+        }
+        const double dg = 1.0 / (Ros4::gamma * h);
+        double a[NP];
+        {
+            const double *pk = L.park + lane_fresh();
+#pragma unroll
+            for (int j = 0; j < NP; j++) a[j] = (lane == j ? dg : 0.0) - (j < N ? pk[j * 64] : 0.0);
+        }
+        LU<NP> lu;
+        lu_factor<NP>(a, lu);
+        const double ih = 1.0 / h;
+        const double u1 = lu_solve<NP>(a, lu, f0[0]);
+        park_rows<NP>(L, a);
+        double yt[1] = {y + Ros4::a21 * u1}, ft[1];
+        rhs_wave<1>(M, L, yt, P, ft);
+        unpark_rows<NP>(L, a);
+        const double u2 = lu_solve<NP>(a, lu, ft[0] + (Ros4::c21 * u1) * ih);
+        yt[0] = y + Ros4::a31 * u1 + Ros4::a32 * u2;
+        rhs_wave<1>(M, L, yt, P, ft);
+        unpark_rows<NP>(L, a);
+        const double u3 = lu_solve<NP>(a, lu, ft[0] + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
+        const double u4 = lu_solve<NP>(a, lu, ft[0] + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
+        ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
+        e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
+        return lu.ok;
+    }
+};
+
 // ---------------------------------------------------------------------------------------
 // FP32 factorisation with FP64 residual refinement
 // ---------------------------------------------------------------------------------------
@@ -746,6 +803,21 @@ struct Ros4Adapter {
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P, double h,
                                 double (&yn)[1], double (&e)[1], const IntOpts &) {
         return Ros4Wave<NP>::step(M, L, y[0], P, h, yn[0], e[0]);
+    }
+};
+
+template <int NP>
+struct Ros4AdapterFD {
+    static constexpr int RPL = 1;
+    static constexpr int NSMAX = NP - 1;
+    static constexpr bool JAC = false;      // no d wdot/dC staging: only source-term evaluations
+    static constexpr int WIN = 0;
+    static constexpr bool PARK = true;
+    static constexpr int PARK_ROWS = NP;
+    static constexpr double qinv = 0.25;
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P,
+                                                double h, double (&yn)[1], double (&e)[1], const IntOpts &o) {
+        return Ros4WaveFD<NP>::step(M, L, y[0], P, h, yn[0], e[0], o);
     }
 };
 
@@ -1019,9 +1091,10 @@ bool wave_supported(const DevMech &M, int method, int precision) {
 }
 
 size_t wave_ws_bytes(const DevMech &M, int cus) {
-    // parked FP64 LU rows of every resident wavefront (FP64 ROS4 with 32 < NP <= 64)
+    // parked FP64 rows of every resident wavefront (FP64 ROS4 with NP > 32, or any NP <= 64 with
+    // the forward-difference Jacobian)
     const int np = pad_np(M.N);
-    if (np <= 32 || np > 64) return 256;
+    if (np > 64) return 256;
     return 256 + size_t(cus) * kWaveMaxPerCu * size_t(np) * 64 * sizeof(double);
 }
 
@@ -1052,6 +1125,17 @@ int launch_integrate_wave(int method, const DevMech &M, int64_t n, double *y, in
     if (method == 1) {
         if (M.N <= 64) return launch_int<Rkf45S<1>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
         return launch_int<Rkf45S<2>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+    }
+    if (o.jacobian == CK_JAC_FD) {
+        if (o.precision != CK_PREC_FP64) return CK_EUNSUPPORTED;
+        switch (pad_np(M.N)) {
+#define CK_CASEFD(NPV) \
+    case NPV: return launch_int<Ros4AdapterFD<NPV>>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+            CK_CASEFD(8) CK_CASEFD(16) CK_CASEFD(24) CK_CASEFD(32) CK_CASEFD(40) CK_CASEFD(48) CK_CASEFD(56)
+            CK_CASEFD(64)
+#undef CK_CASEFD
+            default: return CK_EUNSUPPORTED;
+        }
     }
     if (o.precision == CK_PREC_FP32_REFINE) {
         switch (pad_np(M.N)) {

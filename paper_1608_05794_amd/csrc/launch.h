@@ -9,7 +9,7 @@ namespace ck {
 struct IntOpts {
     double rtol, atol, h0, h_fixed;
     int64_t max_steps;
-    int32_t precision, refine_sweeps, blocks_per_cu;
+    int32_t precision, refine_sweeps, blocks_per_cu, jacobian;
 };
 
 // lane-per-reactor family (k_lane.hip)
