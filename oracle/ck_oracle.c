@@ -420,17 +420,12 @@ static double dprod(const double *C, const int *sp, const int *nu, int ns, int l
     return found ? p : 0.0;
 }
 
-/* Analytic Jacobian J = df/dy (row-major N x N) at y; also returns f. */
-static void jacobian(const orc_mech *m, orc_work *w, const double *y, double P, double *J, double *f)
+/* JC[k][l] = d wdot_k / d C_l at fixed T and dwT[k] = d wdot_k / dT at fixed C, from the
+ * per-reaction quantities of the last source-term evaluation (w->rates, w->st). */
+static void rate_derivatives(const orc_mech *m, orc_work *w, double *JC, double *dwT)
 {
-    const int n = m->nsp, N = n + 1;
+    const int n = m->nsp;
     orc_state *st = &w->st;
-    source_term(m, w, y, P, f);
-    const double T = st->T, rho = st->rho, Wbar = st->Wbar, cp = st->cp_mass, R = m->R;
-
-    /* JC[k][l] = d wdot_k / d C_l at fixed T;  dwT[k] = d wdot_k / dT at fixed C */
-    double *JC = calloc((size_t)n * n, sizeof(double));
-    double *dwT = calloc(n, sizeof(double));
     for (int i = 0; i < m->nrxn; i++) {
         const orc_rxn *r = &m->rx[i];
         const orc_rate *q = &w->rates[i];
@@ -450,6 +445,18 @@ static void jacobian(const orc_mech *m, orc_work *w, const double *y, double P, 
             dwT[k] += v * dqT;
         }
     }
+}
+
+/* Analytic Jacobian J = df/dy (row-major N x N) at y; also returns f. */
+static void jacobian(const orc_mech *m, orc_work *w, const double *y, double P, double *J, double *f)
+{
+    const int n = m->nsp, N = n + 1;
+    orc_state *st = &w->st;
+    source_term(m, w, y, P, f);
+    const double T = st->T, rho = st->rho, Wbar = st->Wbar, cp = st->cp_mass, R = m->R;
+    double *JC = calloc((size_t)n * n, sizeof(double));
+    double *dwT = calloc(n, sizeof(double));
+    rate_derivatives(m, w, JC, dwT);
     /* chain rule through C(T, Y) and rho(T, Y) */
     double *JCC = calloc(n, sizeof(double));     /* sum_l JC[k][l] C_l */
     for (int k = 0; k < n; k++) {
@@ -489,6 +496,88 @@ static void jacobian(const orc_mech *m, orc_work *w, const double *y, double P, 
     free(JC); free(dwT); free(JCC);
 }
 
+/* Constant-volume reactor (Section 3: the constant-volume form uses c_v and the internal energies
+ * in place of c_p and the enthalpies).  State (T, Y); the density rho is fixed and the pressure
+ * follows from the ideal gas:
+ *   C_k = rho Y_k / W_k,  f_Yk = W_k wdot_k / rho,
+ *   f_T = -sum_k U_k wdot_k / (rho c_v),  U_k = H_k - R T,  c_v = sum_k Y_k (cp_k - R) / W_k. */
+static void mixture_state_cv(const orc_mech *m, const double *y, double rho, orc_state *st)
+{
+    const int n = m->nsp;
+    const double T = y[0];
+    double S = 0.0;
+    for (int k = 0; k < n; k++) S += y[1 + k] / m->W[k];
+    st->T = T;
+    st->rho = rho;
+    st->Wbar = 1.0 / S;
+    st->P = rho * m->R * T * S;
+    st->cp_mass = 0.0;   /* holds c_v in this form */
+    for (int k = 0; k < n; k++) {
+        st->C[k] = rho * y[1 + k] / m->W[k];
+        species_thermo(m, k, T, &st->cpR[k], &st->hRT[k], &st->sR[k], &st->dcpR[k]);
+        st->cp_mass += y[1 + k] * (st->cpR[k] - 1.0) * m->R / m->W[k];
+    }
+}
+
+static void source_term_cv(const orc_mech *m, orc_work *w, const double *y, double rho, double *f)
+{
+    const int n = m->nsp;
+    orc_state *st = &w->st;
+    mixture_state_cv(m, y, rho, st);
+    for (int k = 0; k < n; k++) st->wdot[k] = 0.0;
+    for (int i = 0; i < m->nrxn; i++) {
+        const orc_rxn *r = &m->rx[i];
+        orc_rate *q = &w->rates[i];
+        reaction_rate(m, r, st, q);
+        double qi = q->c * (q->kf * q->pf - q->kr * q->pr);
+        for (int j = 0; j < r->nr; j++) st->wdot[r->rsp[j]] -= r->rnu[j] * qi;
+        for (int j = 0; j < r->np; j++) st->wdot[r->psp[j]] += r->pnu[j] * qi;
+    }
+    double Q = 0.0;
+    for (int k = 0; k < n; k++) {
+        f[1 + k] = m->W[k] * st->wdot[k] / rho;
+        Q += m->R * st->T * (st->hRT[k] - 1.0) * st->wdot[k];
+    }
+    f[0] = -Q / (rho * st->cp_mass);
+}
+
+/* Analytic Jacobian of the constant-volume form.  With rho fixed, C depends on Y only:
+ *   dC_k/dY_j = delta_kj rho / W_k,  dC/dT = 0,
+ *   df_Yk/dY_j = (W_k / W_j) JC[k][j],  df_Yk/dT = (W_k / rho) dwT[k],
+ *   df_T/dY_j = -[(rho / W_j) sum_k U_k JC[k][j] + f_T rho R (cp_j/R - 1) / W_j] / (rho c_v),
+ *   df_T/dT   = -[sum_k R (cp_k/R - 1) wdot_k + sum_k U_k dwT[k] + f_T rho sum_k Y_k R dcp_k/W_k] / (rho c_v). */
+static void jacobian_cv(const orc_mech *m, orc_work *w, const double *y, double rho, double *J, double *f)
+{
+    const int n = m->nsp, N = n + 1;
+    orc_state *st = &w->st;
+    source_term_cv(m, w, y, rho, f);
+    const double T = st->T, cv = st->cp_mass, R = m->R;
+    double *JC = calloc((size_t)n * n, sizeof(double));
+    double *dwT = calloc(n, sizeof(double));
+    rate_derivatives(m, w, JC, dwT);
+    for (int k = 0; k < n; k++) {
+        for (int j = 0; j < n; j++) J[(1 + k) * N + 1 + j] = (m->W[k] / m->W[j]) * JC[k * n + j];
+        J[(1 + k) * N + 0] = (m->W[k] / rho) * dwT[k];
+    }
+    const double D = rho * cv, fT = f[0];
+    for (int j = 0; j < n; j++) {
+        double s = 0.0;
+        for (int k = 0; k < n; k++) s += R * T * (st->hRT[k] - 1.0) * JC[k * n + j];
+        const double dQ = (rho / m->W[j]) * s;
+        const double dD = rho * R * (st->cpR[j] - 1.0) / m->W[j];
+        J[0 * N + 1 + j] = -(dQ + fT * dD) / D;
+    }
+    {
+        double dQ = 0.0, sdcp = 0.0;
+        for (int k = 0; k < n; k++) {
+            dQ += R * (st->cpR[k] - 1.0) * st->wdot[k] + R * T * (st->hRT[k] - 1.0) * dwT[k];
+            sdcp += y[1 + k] * R * st->dcpR[k] / m->W[k];
+        }
+        J[0] = -(dQ + fT * rho * sdcp) / D;
+    }
+    free(JC); free(dwT);
+}
+
 /* ------------------------------------------------------------------------- */
 /* problems: chemistry or a dense linear test system y' = A y                */
 /* ------------------------------------------------------------------------- */
@@ -501,13 +590,17 @@ typedef struct {
     long nfev, njev;
     int jac_fd;               /* ROS4 Jacobian: 0 analytic, 1 forward differences */
     double rtol, atol;        /* error weights of the difference increments */
+    int cv;                   /* chemistry: 0 constant pressure (P = pressure), 1 constant volume (P = density) */
 } orc_problem;
 
 static void prob_f(orc_problem *p, const double *y, double *f)
 {
     p->nfev++;
     if (p->m) {
-        source_term(p->m, p->w, y, p->P, f);
+        if (p->cv)
+            source_term_cv(p->m, p->w, y, p->P, f);
+        else
+            source_term(p->m, p->w, y, p->P, f);
         return;
     }
     for (int i = 0; i < p->N; i++) {
@@ -522,7 +615,10 @@ static void prob_jac(orc_problem *p, const double *y, double *J)
     p->njev++;
     if (p->m) {
         double *f = malloc(sizeof(double) * p->N);
-        jacobian(p->m, p->w, y, p->P, J, f);
+        if (p->cv)
+            jacobian_cv(p->m, p->w, y, p->P, J, f);
+        else
+            jacobian(p->m, p->w, y, p->P, J, f);
         free(f);
         return;
     }
@@ -726,7 +822,7 @@ typedef struct {
     double h_fixed;     /* > 0: fixed-step mode, every step accepted */
     int64_t max_steps;  /* attempted steps */
     int32_t jac_fd;     /* ROS4 Jacobian: 0 analytic, 1 forward differences */
-    int32_t pad;
+    int32_t cv;         /* 0 constant pressure, 1 constant volume (the P array then holds densities) */
 } orc_opts;
 
 enum { ST_OK = 0, ST_MAX_STEPS = 1, ST_H_UNDERFLOW = 2, ST_NONFINITE = 3 };
@@ -775,6 +871,7 @@ static int integrate_one(orc_problem *p, int method, double *y, double *t_io, do
     const int N = p->N;
     const double q = (method == 0) ? 4.0 : 5.0;   /* error estimate is O(h^q) */
     p->jac_fd = o->jac_fd;
+    p->cv = p->m ? o->cv : 0;
     p->rtol = o->rtol;
     p->atol = o->atol;
     step_work sw;
@@ -877,6 +974,37 @@ void orc_rhs(const orc_mech *m, int64_t n, const double *y, const double *P, dou
     }
 }
 
+/* Constant-volume source term and Jacobian (rho[r]: density of reactor r, kg/m^3). */
+void orc_rhs_cv(const orc_mech *m, int64_t n, const double *y, const double *rho, double *dydt, int nthreads)
+{
+    const int N = m->nsp + 1;
+    set_threads(nthreads);
+#pragma omp parallel
+    {
+        orc_work w;
+        work_init(m, &w);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t r = 0; r < n; r++) source_term_cv(m, &w, y + r * N, rho[r], dydt + r * N);
+        work_free(&w);
+    }
+}
+
+void orc_jac_cv(const orc_mech *m, int64_t n, const double *y, const double *rho, double *jac, int nthreads)
+{
+    const int N = m->nsp + 1;
+    set_threads(nthreads);
+#pragma omp parallel
+    {
+        orc_work w;
+        work_init(m, &w);
+        double *f = malloc(sizeof(double) * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t r = 0; r < n; r++) jacobian_cv(m, &w, y + r * N, rho[r], jac + r * (int64_t)N * N, f);
+        free(f);
+        work_free(&w);
+    }
+}
+
 void orc_jac(const orc_mech *m, int64_t n, const double *y, const double *P, double *jac, int nthreads)
 {
     const int N = m->nsp + 1;
@@ -908,7 +1036,7 @@ void orc_jac_fd(const orc_mech *m, int64_t n, const double *y, const double *P, 
         work_init(m, &w);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t r = 0; r < n; r++) {
-            orc_problem p = {N, m, P[r], &w, NULL, 0, 0, 1, rtol, atol};
+            orc_problem p = {N, m, P[r], &w, NULL, 0, 0, 1, rtol, atol, 0};
             jacobian_fd(&p, y + r * N, h, jac + r * N * N);
         }
         work_free(&w);
@@ -950,7 +1078,7 @@ int orc_integrate(const orc_mech *m, int method, int64_t n, double *y, const dou
         work_init(m, &w);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t r = 0; r < n; r++) {
-            orc_problem p = {N, m, P[r], &w, NULL, 0, 0, 0, 0.0, 0.0};
+            orc_problem p = {N, m, P[r], &w, NULL, 0, 0, 0, 0.0, 0.0, 0};
             status[r] = integrate_one(&p, method, y + r * N, t ? t + r : NULL, h ? h + r : NULL, t_end[r], o,
                                       nacc + r, nrej + r);
         }
@@ -963,7 +1091,7 @@ int orc_integrate(const orc_mech *m, int method, int64_t n, double *y, const dou
 int orc_integrate_linear(int method, int N, const double *A, double *y, double t_end, double *t, double *h,
                          const orc_opts *o, int32_t *status, int32_t *nacc, int32_t *nrej, long *nfev)
 {
-    orc_problem p = {N, NULL, 0.0, NULL, A, 0, 0, 0, 0.0, 0.0};
+    orc_problem p = {N, NULL, 0.0, NULL, A, 0, 0, 0, 0.0, 0.0, 0};
     *status = integrate_one(&p, method, y, t, h, t_end, o, nacc, nrej);
     if (nfev) *nfev = p.nfev;
     return 0;
@@ -972,7 +1100,7 @@ int orc_integrate_linear(int method, int N, const double *A, double *y, double t
 /* One step of either method on y' = A y from y (no control): returns y* and the error vector. */
 int orc_step_linear(int method, int N, const double *A, const double *y, double h, double *ynew, double *err)
 {
-    orc_problem p = {N, NULL, 0.0, NULL, A, 0, 0, 0, 0.0, 0.0};
+    orc_problem p = {N, NULL, 0.0, NULL, A, 0, 0, 0, 0.0, 0.0, 0};
     step_work sw;
     sw.ytmp = malloc(sizeof(double) * N);
     sw.f = malloc(sizeof(double) * N);

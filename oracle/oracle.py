@@ -18,7 +18,7 @@ _lib = None
 
 class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double),
-                ("h_fixed", C.c_double), ("max_steps", C.c_int64), ("jac_fd", C.c_int32), ("pad", C.c_int32)]
+                ("h_fixed", C.c_double), ("max_steps", C.c_int64), ("jac_fd", C.c_int32), ("cv", C.c_int32)]
 
 
 def lib():
@@ -35,6 +35,8 @@ def lib():
         L.orc_thermo.argtypes = [vp, C.c_double, dp, dp, dp]
         L.orc_rhs.argtypes = [vp, i64, dp, dp, dp, C.c_int]
         L.orc_jac.argtypes = [vp, i64, dp, dp, dp, C.c_int]
+        L.orc_rhs_cv.argtypes = [vp, i64, dp, dp, dp, C.c_int]
+        L.orc_jac_cv.argtypes = [vp, i64, dp, dp, dp, C.c_int]
         L.orc_jac_fd.argtypes = [vp, i64, dp, dp, C.c_double, C.c_double, C.c_double, dp, C.c_int]
         L.orc_rates.argtypes = [vp, dp, C.c_double, dp, dp, dp, dp, dp]
         L.orc_stoich.argtypes = [vp, C.POINTER(C.c_int)]
@@ -60,10 +62,11 @@ METHODS = {"ros4": 0, "rkf45": 1}
 
 
 JACOBIANS = {"analytic": 0, "fd": 1}
+REACTORS = {"cp": 0, "cv": 1}     # constant pressure (P in Pa) / constant volume (P holds densities, kg/m^3)
 
 
-def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000, jacobian="analytic"):
-    return Opts(rtol, atol, h0, h_fixed, max_steps, JACOBIANS[jacobian], 0)
+def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000, jacobian="analytic", reactor="cp"):
+    return Opts(rtol, atol, h0, h_fixed, max_steps, JACOBIANS[jacobian], REACTORS[reactor])
 
 
 class Mechanism:
@@ -110,23 +113,26 @@ class Mechanism:
         return nu
 
     # --- batch calls (SoA in, SoA out) ------------------------------------------------------
-    def rhs(self, y, P, nthreads=0):
+    def rhs(self, y, P, nthreads=0, reactor="cp"):
+        """dy/dt [N][n]; P holds pressures (Pa) for reactor="cp", densities (kg/m^3) for "cv"."""
         y = np.asarray(y, dtype=np.float64)
         n = y.shape[1]
         aos = np.array(y.T, dtype=np.float64, order="C", copy=True)
         out = np.zeros_like(aos)
-        Pa = np.ascontiguousarray(P, dtype=np.float64)
-        lib().orc_rhs(self._h, n, _d(aos), _d(Pa), _d(out), nthreads)
+        Pa = np.ascontiguousarray(np.broadcast_to(P, (n,)), dtype=np.float64)
+        fn = lib().orc_rhs if reactor == "cp" else lib().orc_rhs_cv
+        fn(self._h, n, _d(aos), _d(Pa), _d(out), nthreads)
         return np.ascontiguousarray(out.T)
 
-    def jac(self, y, P, nthreads=0):
+    def jac(self, y, P, nthreads=0, reactor="cp"):
         """Returns J as [n][N][N] (reactor, row i = df_i, column j = d/dy_j)."""
         y = np.asarray(y, dtype=np.float64)
         n = y.shape[1]
         aos = np.array(y.T, dtype=np.float64, order="C", copy=True)
         out = np.zeros((n, self.N, self.N))
-        Pa = np.ascontiguousarray(P, dtype=np.float64)
-        lib().orc_jac(self._h, n, _d(aos), _d(Pa), _d(out), nthreads)
+        Pa = np.ascontiguousarray(np.broadcast_to(P, (n,)), dtype=np.float64)
+        fn = lib().orc_jac if reactor == "cp" else lib().orc_jac_cv
+        fn(self._h, n, _d(aos), _d(Pa), _d(out), nthreads)
         return out
 
     def jac_fd(self, y, P, h, rtol=1e-8, atol=1e-12, nthreads=0):
@@ -140,7 +146,7 @@ class Mechanism:
         return out
 
     def integrate(self, y, P, t_end, method="ros4", rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0,
-                  max_steps=1_000_000, t=None, h=None, nthreads=0, jacobian="analytic"):
+                  max_steps=1_000_000, t=None, h=None, nthreads=0, jacobian="analytic", reactor="cp"):
         """Integrate each reactor to t_end.  Returns dict(y, t, h, status, n_accept, n_reject)."""
         y = np.asarray(y, dtype=np.float64)
         n = y.shape[1]
@@ -150,7 +156,7 @@ class Mechanism:
         tt = np.zeros(n) if t is None else np.array(t, dtype=np.float64)
         hh = np.zeros(n) if h is None else np.array(h, dtype=np.float64)
         st, na, nr = (np.zeros(n, dtype=np.int32) for _ in range(3))
-        o = make_opts(rtol, atol, h0, h_fixed, max_steps, jacobian)
+        o = make_opts(rtol, atol, h0, h_fixed, max_steps, jacobian, reactor)
         lib().orc_integrate(self._h, METHODS[method], n, _d(aos), _d(Pa), _d(te), _d(tt), _d(hh), C.byref(o),
                             _i(st), _i(na), _i(nr), nthreads)
         return dict(y=np.ascontiguousarray(aos.T), t=tt, h=hh, status=st, n_accept=na, n_reject=nr)
