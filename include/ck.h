@@ -59,6 +59,15 @@ enum {
                               wavefronts, persistent work queue, Gauss-Jordan inverse in registers */
 };
 
+/* Reactor form (Section 3).  Constant pressure: p[] holds pressures (Pa); the density follows
+ * the state.  Constant volume: p[] holds densities (kg/m^3), fixed per reactor; the energy
+ * equation uses c_v and the internal energies (wavefront kernels, N <= 64 for the Jacobian and
+ * ROS4). */
+enum {
+    CK_REACTOR_CONST_P = 0,
+    CK_REACTOR_CONST_V = 1
+};
+
 /* Jacobian used by ROS4. */
 enum {
     CK_JAC_ANALYTIC = 0,   /* analytic Jacobian (chain rule through the rates of progress) */
@@ -85,11 +94,11 @@ typedef struct {
     int32_t blocks_per_cu; /* persistent kernels (WAVE, GROUP): resident workgroups per compute unit;
                               0 = as many as registers and LDS allow (larger values are clamped) */
     int32_t jacobian;      /* CK_JAC_* (ROS4 only) */
-    int32_t reserved;      /* must be 0 */
+    int32_t reactor;       /* CK_REACTOR_*: with CK_REACTOR_CONST_V the p array holds densities */
 } ck_opts;
 
 /* Fills *o with the defaults: rtol 1e-8, atol 1e-12, h0 0, h_fixed 0, max_steps 1e6,
- * CK_KERNEL_AUTO, CK_PREC_FP64, refine_sweeps 3, blocks_per_cu 0, CK_JAC_ANALYTIC. */
+ * CK_KERNEL_AUTO, CK_PREC_FP64, refine_sweeps 3, blocks_per_cu 0, CK_JAC_ANALYTIC, CK_REACTOR_CONST_P. */
 void ck_opts_default(ck_opts *o);
 
 const char *ck_strerror(int code);
@@ -169,12 +178,14 @@ int ck_integrate_rkf45(const ck_mech *m, int64_t n, double *y, int64_t ld, const
  * CK_KERNEL_AUTO: the library's choice).  ck_rhs_eval uses CK_KERNEL_AUTO
  * (wavefront); ck_jacobian_eval uses CK_KERNEL_LANE.  CK_KERNEL_WAVE
  * Jacobians need N <= 64 (CK_EUNSUPPORTED otherwise).  The lane family uses
- * a library-owned scratch buffer sized for n.
+ * a library-owned scratch buffer sized for n.  reactor: CK_REACTOR_CONST_P (p =
+ * pressures) or CK_REACTOR_CONST_V (p = densities; wavefront family only,
+ * CK_EUNSUPPORTED with CK_KERNEL_LANE).
  */
 int ck_rhs_eval_ex(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
-                   int32_t kernel, void *stream);
+                   int32_t kernel, int32_t reactor, void *stream);
 int ck_jacobian_eval_ex(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
-                        int32_t kernel, void *stream);
+                        int32_t kernel, int32_t reactor, void *stream);
 
 #ifdef __cplusplus
 }

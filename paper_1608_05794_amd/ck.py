@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libck.so")
 KERNELS = {"auto": 0, "lane": 1, "wave": 2, "group": 3}
 PRECISIONS = {"fp64": 0, "fp32_refine": 1}
 JACOBIANS = {"analytic": 0, "fd": 1}
+REACTORS = {"cp": 0, "cv": 1}   # constant pressure (p = pressures, Pa) / constant volume (p = densities, kg/m^3)
 STATUS = {0: "ok", 1: "max_steps", 2: "h_underflow", 3: "nonfinite"}
 
 
@@ -28,7 +29,7 @@ class CkError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double), ("h_fixed", C.c_double),
                 ("max_steps", C.c_int64), ("kernel", C.c_int32), ("precision", C.c_int32),
-                ("refine_sweeps", C.c_int32), ("blocks_per_cu", C.c_int32), ("jacobian", C.c_int32), ("reserved", C.c_int32)]
+                ("refine_sweeps", C.c_int32), ("blocks_per_cu", C.c_int32), ("jacobian", C.c_int32), ("reactor", C.c_int32)]
 
 
 _lib = None
@@ -53,9 +54,9 @@ def lib():
         L.ck_mechanism_free.argtypes = [vp]
         L.ck_mechanism_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.ck_rhs_eval.argtypes = [vp, i64, dp, i64, dp, dp, vp]
-        L.ck_rhs_eval_ex.argtypes = [vp, i64, dp, i64, dp, dp, C.c_int32, vp]
+        L.ck_rhs_eval_ex.argtypes = [vp, i64, dp, i64, dp, dp, C.c_int32, C.c_int32, vp]
         L.ck_jacobian_eval.argtypes = [vp, i64, dp, i64, dp, dp, vp]
-        L.ck_jacobian_eval_ex.argtypes = [vp, i64, dp, i64, dp, dp, C.c_int32, vp]
+        L.ck_jacobian_eval_ex.argtypes = [vp, i64, dp, i64, dp, dp, C.c_int32, C.c_int32, vp]
         L.ck_workspace_bytes.argtypes = [vp, i64, C.POINTER(Opts)]
         L.ck_workspace_bytes.restype = C.c_size_t
         sig = [vp, i64, dp, i64, dp, dp, dp, dp, C.POINTER(Opts), vp, i32p, i32p, i32p, vp]
@@ -88,7 +89,7 @@ def _state(y, N):
 
 
 def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000, kernel="auto", precision="fp64",
-              refine_sweeps=3, blocks_per_cu=0, jacobian="analytic"):
+              refine_sweeps=3, blocks_per_cu=0, jacobian="analytic", reactor="cp"):
     o = Opts()
     lib().ck_opts_default(C.byref(o))
     o.rtol, o.atol, o.h0, o.h_fixed, o.max_steps = rtol, atol, h0, h_fixed, max_steps
@@ -97,6 +98,7 @@ def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000, k
     o.refine_sweeps = refine_sweeps
     o.blocks_per_cu = blocks_per_cu
     o.jacobian = JACOBIANS[jacobian]
+    o.reactor = REACTORS[reactor]
     return o
 
 
@@ -133,31 +135,32 @@ class Mechanism:
         return int(lib().ck_workspace_bytes(self._h, int(n), C.byref(o)))
 
 
-def rhs(mech, y, p, out=None, kernel=None, stream=None):
-    """dy/dt for every reactor (ck_rhs_eval); y [N, n] float64, p [n] Pa."""
+def rhs(mech, y, p, out=None, kernel=None, stream=None, reactor="cp"):
+    """dy/dt for every reactor (ck_rhs_eval / ck_rhs_eval_ex); y [N, n] float64, p [n]: pressures (Pa)
+    for reactor="cp", densities (kg/m^3) for "cv"."""
     ld = _state(y, mech.N)
     n = y.shape[1]
     out = torch.empty_like(y) if out is None else out
     if out.stride(0) != ld or out.stride(1) != 1:
         raise CkError("output must have the state's strides")
-    if kernel is None:
+    if kernel is None and reactor == "cp":
         _check(lib().ck_rhs_eval(mech.handle, n, _ptr(y), ld, _ptr(p), _ptr(out), _stream(stream)))
     else:
-        _check(lib().ck_rhs_eval_ex(mech.handle, n, _ptr(y), ld, _ptr(p), _ptr(out), KERNELS[kernel],
-                                    _stream(stream)))
+        _check(lib().ck_rhs_eval_ex(mech.handle, n, _ptr(y), ld, _ptr(p), _ptr(out), KERNELS[kernel or "auto"],
+                                    REACTORS[reactor], _stream(stream)))
     return out
 
 
-def jac(mech, y, p, kernel=None, stream=None):
-    """Analytic Jacobian (ck_jacobian_eval): returns [N*N, n] with row (i*N + j) = df_i/dy_j."""
+def jac(mech, y, p, kernel=None, stream=None, reactor="cp"):
+    """Analytic Jacobian (ck_jacobian_eval / _ex): returns [N*N, n] with row (i*N + j) = df_i/dy_j."""
     ld = _state(y, mech.N)
     n = y.shape[1]
     out = torch.empty((mech.N * mech.N, n), dtype=torch.float64, device=y.device)
-    if kernel is None:
+    if kernel is None and reactor == "cp":
         _check(lib().ck_jacobian_eval(mech.handle, n, _ptr(y), ld, _ptr(p), _ptr(out), _stream(stream)))
     else:
-        _check(lib().ck_jacobian_eval_ex(mech.handle, n, _ptr(y), ld, _ptr(p), _ptr(out), KERNELS[kernel],
-                                         _stream(stream)))
+        _check(lib().ck_jacobian_eval_ex(mech.handle, n, _ptr(y), ld, _ptr(p), _ptr(out), KERNELS[kernel or "auto"],
+                                         REACTORS[reactor], _stream(stream)))
     return out
 
 

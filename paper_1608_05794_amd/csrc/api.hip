@@ -63,7 +63,7 @@ int validate_opts(const ck_opts *o, IntOpts &io) {
     if (o->refine_sweeps < 0 || o->refine_sweeps > 3) return CK_EINVAL;
     if (o->blocks_per_cu < 0) return CK_EINVAL;
     if (o->jacobian != CK_JAC_ANALYTIC && o->jacobian != CK_JAC_FD) return CK_EINVAL;
-    if (o->reserved != 0) return CK_EINVAL;
+    if (o->reactor != CK_REACTOR_CONST_P && o->reactor != CK_REACTOR_CONST_V) return CK_EINVAL;
     io.rtol = o->rtol;
     io.atol = o->atol;
     io.h0 = o->h0;
@@ -73,6 +73,7 @@ int validate_opts(const ck_opts *o, IntOpts &io) {
     io.refine_sweeps = o->refine_sweeps;
     io.blocks_per_cu = o->blocks_per_cu;
     io.jacobian = o->jacobian;
+    io.reactor = o->reactor;
     return CK_OK;
 }
 
@@ -83,6 +84,11 @@ int choose_kernel(const ck_mech *m, int method, const ck_opts *o) {
     if (!o) o = &d;
     const bool fp64 = o->precision == CK_PREC_FP64;
     const bool wave_ok = wave_supported(m->dev, method, o->precision);
+    if (o->reactor == CK_REACTOR_CONST_V) {
+        // constant volume: wavefront kernels only
+        if (!wave_ok || (o->kernel != CK_KERNEL_AUTO && o->kernel != CK_KERNEL_WAVE)) return CK_EUNSUPPORTED;
+        return CK_KERNEL_WAVE;
+    }
     if (method == 0 && o->jacobian == CK_JAC_FD) {
         // forward-difference Jacobian: wavefront kernel, FP64 only
         if (!fp64 || !wave_ok || (o->kernel != CK_KERNEL_AUTO && o->kernel != CK_KERNEL_WAVE))
@@ -150,7 +156,7 @@ extern "C" void ck_opts_default(ck_opts *o) {
     o->refine_sweeps = 3;
     o->blocks_per_cu = 0;
     o->jacobian = CK_JAC_ANALYTIC;
-    o->reserved = 0;
+    o->reactor = CK_REACTOR_CONST_P;
 }
 
 extern "C" const char *ck_strerror(int code) {
@@ -167,10 +173,12 @@ extern "C" const char *ck_strerror(int code) {
 }
 
 extern "C" int ck_rhs_eval_ex(const ck_mech *mc, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
-                              int32_t kernel, void *stream) {
+                              int32_t kernel, int32_t reactor, void *stream) {
     ck_mech *m = const_cast<ck_mech *>(mc);
     if (!check_state_args(m, n, y, ld, p, dydt)) return CK_EINVAL;
     if (kernel < CK_KERNEL_AUTO || kernel > CK_KERNEL_WAVE) return CK_EINVAL;
+    if (reactor != CK_REACTOR_CONST_P && reactor != CK_REACTOR_CONST_V) return CK_EINVAL;
+    if (reactor == CK_REACTOR_CONST_V && kernel == CK_KERNEL_LANE) return CK_EUNSUPPORTED;
     if (n == 0) return CK_OK;
     DeviceGuard g(m->device);
     if (!g.ok) return CK_EHIP;
@@ -181,24 +189,29 @@ extern "C" int ck_rhs_eval_ex(const ck_mech *mc, int64_t n, const double *y, int
         if (rc != CK_OK) return rc;
         return launch_rhs_lane(m->dev, n, y, ld, p, dydt, static_cast<double *>(ws), round_up(n, 64), s);
     }
-    return launch_rhs_wave(m->dev, n, y, ld, p, dydt, s);
+    return launch_rhs_wave(m->dev, n, y, ld, p, dydt, reactor, s);
 }
 
 extern "C" int ck_rhs_eval(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
                            void *stream) {
-    return ck_rhs_eval_ex(m, n, y, ld, p, dydt, CK_KERNEL_AUTO, stream);
+    return ck_rhs_eval_ex(m, n, y, ld, p, dydt, CK_KERNEL_AUTO, CK_REACTOR_CONST_P, stream);
 }
 
 extern "C" int ck_jacobian_eval_ex(const ck_mech *mc, int64_t n, const double *y, int64_t ld, const double *p,
-                                   double *jac, int32_t kernel, void *stream) {
+                                   double *jac, int32_t kernel, int32_t reactor, void *stream) {
     ck_mech *m = const_cast<ck_mech *>(mc);
     if (!check_state_args(m, n, y, ld, p, jac)) return CK_EINVAL;
     if (kernel < CK_KERNEL_AUTO || kernel > CK_KERNEL_WAVE) return CK_EINVAL;
+    if (reactor != CK_REACTOR_CONST_P && reactor != CK_REACTOR_CONST_V) return CK_EINVAL;
+    if (reactor == CK_REACTOR_CONST_V) {
+        if (kernel == CK_KERNEL_LANE) return CK_EUNSUPPORTED;
+        kernel = CK_KERNEL_WAVE;
+    }
     if (n == 0) return CK_OK;
     DeviceGuard g(m->device);
     if (!g.ok) return CK_EHIP;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (kernel == CK_KERNEL_WAVE) return launch_jac_wave(m->dev, n, y, ld, p, jac, s);
+    if (kernel == CK_KERNEL_WAVE) return launch_jac_wave(m->dev, n, y, ld, p, jac, reactor, s);
     void *ws = nullptr;
     int rc = cached_ws(m, lane_bytes(m, n, 0), &ws);
     if (rc != CK_OK) return rc;
@@ -207,7 +220,7 @@ extern "C" int ck_jacobian_eval_ex(const ck_mech *mc, int64_t n, const double *y
 
 extern "C" int ck_jacobian_eval(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
                                 void *stream) {
-    return ck_jacobian_eval_ex(m, n, y, ld, p, jac, CK_KERNEL_LANE, stream);
+    return ck_jacobian_eval_ex(m, n, y, ld, p, jac, CK_KERNEL_LANE, CK_REACTOR_CONST_P, stream);
 }
 
 extern "C" size_t ck_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts *o) {

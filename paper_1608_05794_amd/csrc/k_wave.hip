@@ -49,6 +49,7 @@ struct Lds {
     double *C, *G, *H, *WD, *IW, *VX, *JC, *TB, *DWT, *TROW;
     double *park;   // this wavefront's slice of the workspace for parked LU rows ([NP][64]), or null
     int ldj;
+    int cv;         // 0: constant pressure (p = pressure); 1: constant volume (p = density)
 };
 
 __host__ __device__ inline int ldj_of(int win) { return win | 1; }
@@ -77,6 +78,7 @@ __device__ __forceinline__ Lds carve(double *b, int ns, bool jac, int win) {
         L.JC = L.TB = L.DWT = L.TROW = nullptr;
     }
     L.park = nullptr;
+    L.cv = 0;
     return L;
 }
 __device__ __forceinline__ Lds carve(double *b, int ns, bool jac) { return carve(b, ns, jac, ns); }
@@ -119,9 +121,14 @@ __device__ __forceinline__ void species_pass(const DevMech &M, const double (&y)
         if (k >= 0) sy += y[c] * M.invW()[k];
     }
     const double S = wsum(sy);
-    x.rho = P / (M.R * T * S);
+    if (L.cv) {   // constant volume: P holds the (fixed) density
+        x.rho = P;
+        x.Ctot = P * S;
+    } else {
+        x.rho = P / (M.R * T * S);
+        x.Ctot = P * x.t.invT / M.R;
+    }
     x.Wbar = 1.0 / S;
-    x.Ctot = P * x.t.invT / M.R;
     double cpp = 0.0;
 #pragma unroll
     for (int c = 0; c < RPL; c++) {
@@ -224,11 +231,13 @@ __device__ __forceinline__ void reaction_pass(const DevMech &M, const Lds &L, co
     reaction_pass<JAC>(M, L, t, Ctot, 0, M.nsp, true);
 }
 
-// Eqs. ydot and tdot from the accumulated production rates.
+// Eqs. ydot and tdot from the accumulated production rates.  Constant volume: internal energies
+// U_k = H_k - R T and c_v = c_p - R / Wbar in place of H_k and c_p.
 template <int RPL>
 __device__ __forceinline__ void finish_rhs(const DevMech &M, const Lds &L, const Mix<RPL> &x, double (&f)[RPL]) {
     const int ns = M.nsp;
     const int lane = lane_fresh();
+    const double shift = L.cv ? 1.0 : 0.0;
     double qp = 0.0;
 #pragma unroll
     for (int c = 0; c < RPL; c++) {
@@ -236,13 +245,14 @@ __device__ __forceinline__ void finish_rhs(const DevMech &M, const Lds &L, const
         if (k >= 0) {
             const double wd = L.WD[k];
             f[c] = M.W()[k] * wd / x.rho;
-            qp += M.R * x.t.T * x.h[c] * wd;
+            qp += M.R * x.t.T * (x.h[c] - shift) * wd;
         } else {
             f[c] = 0.0;
         }
     }
     const double Q = wsum(qp);
-    if (lane == 0) f[0] = -Q / (x.rho * x.cpm);
+    const double heat_cap = L.cv ? x.cpm - M.R / x.Wbar : x.cpm;
+    if (lane == 0) f[0] = -Q / (x.rho * heat_cap);
 }
 
 template <int RPL>
@@ -260,52 +270,88 @@ struct JRow {
     double alpha, beta, c0;
 };
 
-// Chain rule from (d wdot/dC, d wdot/dT) to J = df/dy (N <= 64, one row per lane).
+// Chain rule from (d wdot/dC at fixed T, d wdot/dT at fixed C) to J = df/dy, for the lane's
+// species row k (lane k + 1) and the lane's entry of the temperature row.  Inputs: jcc =
+// sum_l JC[k][l] C_l (third-body rank-one part excluded), colH = sum_r h_r JC[r][k] and colJ =
+// sum_r JC[r][k] (h_r = H_r / (R T)).  The species row is J[k+1][0] = col0,
+// J[k+1][1+j] = (alpha JC[k][j] + beta) / W_j; trow is J[0][1+k] and J00 = J[0][0].
+// Constant pressure: C = rho Y / W with rho = P Wbar / (R T); constant volume: rho fixed, U_k and
+// c_v in place of H_k and c_p.
+struct Chain {
+    double alpha, beta, col0, trow, J00;
+};
+__device__ __forceinline__ Chain chain_rule(const DevMech &M, const Lds &L, const Mix<1> &x, bool valid, int k,
+                                            double y0, double fT, double jcc, double colH, double colJ) {
+    const double RT = M.R * x.t.T;
+    double TBk = 0.0, WDk = 0.0, DWTk = 0.0;
+    if (valid) {
+        TBk = L.TB[k];
+        WDk = L.WD[k];
+        DWTk = L.DWT[k];
+    }
+    const double Wk = valid ? M.W()[k] : 0.0, iWk = valid ? M.invW()[k] : 0.0;
+    const double sdcp = wsum(valid ? y0 * M.R * x.dcp[0] * iWk : 0.0);
+    Chain c;
+    if (!L.cv) {
+        jcc += TBk * x.Ctot;
+        const double resid = WDk - jcc;
+        const double Hk = RT * x.h[0];
+        const double sumHTB = wsum(valid ? Hk * TBk : 0.0);
+        const double sumHJCC = wsum(valid ? Hk * jcc : 0.0);
+        const double dQT = wsum(valid ? M.R * x.cp[0] * WDk + Hk * (DWTk - jcc * x.t.invT) : 0.0);
+        const double D = x.rho * x.cpm;
+        const double dQ = iWk * (x.rho * (RT * colH + sumHTB) - x.Wbar * sumHJCC);
+        const double dD = x.rho * iWk * (M.R * x.cp[0] - x.cpm * x.Wbar);
+        c.trow = valid ? -(dQ + fT * dD) / D : 0.0;
+        c.J00 = -(dQT + fT * (-x.rho * x.cpm * x.t.invT + x.rho * sdcp)) / D;
+        c.alpha = Wk;
+        c.beta = valid ? Wk * TBk + Wk * x.Wbar * resid / x.rho : 0.0;
+        c.col0 = valid ? (Wk / x.rho) * (DWTk + resid * x.t.invT) : 0.0;
+    } else {
+        const double Uk = RT * (x.h[0] - 1.0);
+        const double sumUTB = wsum(valid ? Uk * TBk : 0.0);
+        const double dQT = wsum(valid ? M.R * (x.cp[0] - 1.0) * WDk + Uk * DWTk : 0.0);
+        const double D = x.rho * (x.cpm - M.R / x.Wbar);
+        const double dQ = iWk * x.rho * (RT * (colH - colJ) + sumUTB);
+        const double dD = x.rho * iWk * M.R * (x.cp[0] - 1.0);
+        c.trow = valid ? -(dQ + fT * dD) / D : 0.0;
+        c.J00 = -(dQT + fT * x.rho * sdcp) / D;
+        c.alpha = Wk;
+        c.beta = Wk * TBk;
+        c.col0 = valid ? (Wk / x.rho) * DWTk : 0.0;
+    }
+    return c;
+}
+
+// Row descriptor of J for N <= 64, one row per lane (Jacobian pieces staged whole in LDS).
 __device__ __forceinline__ JRow jac_prepare(const DevMech &M, const Lds &L, const Mix<1> &x, double y0, double fT) {
     const int ns = M.nsp, lane = lane_fresh();
     const int k = slot_species(0, ns, lane);
     const bool valid = k >= 0;
-    const double T = x.t.T, RT = M.R * T;
-    double jcc = 0.0, colH = 0.0, resid = 0.0, a = 0.0, col0 = 0.0, TBk = 0.0, WDk = 0.0, DWTk = 0.0;
+    double jcc = 0.0, colH = 0.0, colJ = 0.0;
     if (valid) {
         const double *row = &L.JC[k * L.ldj];
         for (int j = 0; j < ns; j++) {
             jcc += row[j] * L.C[j];
-            colH += L.H[j] * L.JC[j * L.ldj + k];
+            const double v = L.JC[j * L.ldj + k];
+            colH += L.H[j] * v;
+            colJ += v;
         }
-        TBk = L.TB[k];
-        WDk = L.WD[k];
-        DWTk = L.DWT[k];
-        jcc += TBk * x.Ctot;
-        colH *= RT;
-        resid = WDk - jcc;
-        a = M.W()[k] * x.Wbar * resid / x.rho;
-        col0 = (M.W()[k] / x.rho) * (DWTk + resid * x.t.invT);
     }
-    const double Hk = RT * x.h[0];
-    const double sumHTB = wsum(valid ? Hk * TBk : 0.0);
-    const double sumHJCC = wsum(valid ? Hk * jcc : 0.0);
-    const double dQT = wsum(valid ? M.R * x.cp[0] * WDk + Hk * (DWTk - jcc * x.t.invT) : 0.0);
-    const double sdcp = wsum(valid ? y0 * M.R * x.dcp[0] * M.invW()[k] : 0.0);
-    const double D = x.rho * x.cpm;
-    if (valid) {
-        const double dQ = M.invW()[k] * (x.rho * (colH + sumHTB) - x.Wbar * sumHJCC);
-        const double dD = x.rho * M.invW()[k] * (M.R * x.cp[0] - x.cpm * x.Wbar);
-        L.TROW[k] = -(dQ + fT * dD) / D * M.W()[k];
-    }
-    const double J00 = -(dQT + fT * (-x.rho * x.cpm * x.t.invT + x.rho * sdcp)) / D;
+    const Chain c = chain_rule(M, L, x, valid, k, y0, fT, jcc, colH, colJ);
+    if (valid) L.TROW[k] = c.trow * M.W()[k];
     __syncthreads();
     JRow r;
     if (lane == 0) {
         r.src = L.TROW;
         r.alpha = 1.0;
         r.beta = 0.0;
-        r.c0 = J00;
+        r.c0 = c.J00;
     } else if (valid) {
         r.src = &L.JC[k * L.ldj];
-        r.alpha = M.W()[k];
-        r.beta = M.W()[k] * TBk + a;
-        r.c0 = col0;
+        r.alpha = c.alpha;
+        r.beta = c.beta;
+        r.c0 = c.col0;
     } else {
         r.src = L.TROW;
         r.alpha = 0.0;
@@ -351,7 +397,7 @@ __device__ __forceinline__ void jac_rows_win(const DevMech &M, const Lds &L, dou
     const int lane = lane_fresh();
     const int k = lane - 1;
     const bool valid = lane >= 1 && lane <= ns;
-    double jcc = 0.0, colH = 0.0;
+    double jcc = 0.0, colH = 0.0, colJ = 0.0;
     for (int w = 0; w < NWIN; w++) {
         const int c0 = opaque(w * WIN);
         const int tot = ns * L.ldj;
@@ -370,7 +416,11 @@ __device__ __forceinline__ void jac_rows_win(const DevMech &M, const Lds &L, dou
             pk[(1 + c0 + j) * 64] = v;
         }
         if (valid && k >= c0 && k < c0 + WIN)
-            for (int r = 0; r < ns; r++) colH += L.H[r] * L.JC[r * L.ldj + (k - c0)];
+            for (int r = 0; r < ns; r++) {
+                const double v = L.JC[r * L.ldj + (k - c0)];
+                colH += L.H[r] * v;
+                colJ += v;
+            }
         __syncthreads();
     }
     {
@@ -379,35 +429,10 @@ __device__ __forceinline__ void jac_rows_win(const DevMech &M, const Lds &L, dou
         for (int j = 1; j < NP; j++) a[j] = pk[j * 64];
     }
     f = ff[0];
-    // chain rule from (d wdot/dC, d wdot/dT) to J = df/dy (as in jac_prepare)
-    const double T = x.t.T, RT = M.R * T;
-    double resid = 0.0, ra = 0.0, col0 = 0.0, TBk = 0.0, WDk = 0.0, DWTk = 0.0;
-    if (valid) {
-        TBk = L.TB[k];
-        WDk = L.WD[k];
-        DWTk = L.DWT[k];
-        jcc += TBk * x.Ctot;
-        colH *= RT;
-        resid = WDk - jcc;
-        ra = M.W()[k] * x.Wbar * resid / x.rho;
-        col0 = (M.W()[k] / x.rho) * (DWTk + resid * x.t.invT);
-    }
-    const double Hk = RT * x.h[0];
-    const double sumHTB = wsum(valid ? Hk * TBk : 0.0);
-    const double sumHJCC = wsum(valid ? Hk * jcc : 0.0);
-    const double dQT = wsum(valid ? M.R * x.cp[0] * WDk + Hk * (DWTk - jcc * x.t.invT) : 0.0);
-    const double sdcp = wsum(valid ? y * M.R * x.dcp[0] * M.invW()[k] : 0.0);
-    const double fT = bcast(f, 0);
-    const double D = x.rho * x.cpm;
-    if (valid) {
-        const double dQ = M.invW()[k] * (x.rho * (colH + sumHTB) - x.Wbar * sumHJCC);
-        const double dD = x.rho * M.invW()[k] * (M.R * x.cp[0] - x.cpm * x.Wbar);
-        L.TROW[k] = -(dQ + fT * dD) / D;
-    }
-    const double J00 = -(dQT + fT * (-x.rho * x.cpm * x.t.invT + x.rho * sdcp)) / D;
+    const Chain c = chain_rule(M, L, x, valid, k, y, bcast(f, 0), jcc, colH, colJ);
+    if (valid) L.TROW[k] = c.trow;
+    const double J00 = c.J00, col0 = c.col0, alpha = c.alpha, beta = c.beta;
     __syncthreads();
-    const double alpha = valid ? M.W()[k] : 0.0;
-    const double beta = valid ? M.W()[k] * TBk + ra : 0.0;
     a[0] = (lane == 0 ? dg : 0.0) - (lane == 0 ? J00 : col0);
 #pragma unroll
     for (int j = 1; j < NP; j++) {
@@ -984,9 +1009,10 @@ __device__ __forceinline__ int64_t xcd_reactor(int64_t b, int64_t nb) {
 // ---------------------------------------------------------------------------------------
 template <int RPL>
 __global__ void __launch_bounds__(64) rhs_wave_kernel(DevMech M, int64_t n, const double *y, int64_t ld,
-                                                      const double *p, double *dydt) {
+                                                      const double *p, double *dydt, int cv) {
     extern __shared__ double lds_raw[];
-    const Lds L = carve(lds_raw, M.nsp, false);
+    Lds L = carve(lds_raw, M.nsp, false);
+    L.cv = cv;
     init_lds(M, L);
     const int N = M.N, lane = lane_id();
     const int64_t nb = int64_t(gridDim.x);
@@ -1007,9 +1033,10 @@ __global__ void __launch_bounds__(64) rhs_wave_kernel(DevMech M, int64_t n, cons
 }
 
 __global__ void __launch_bounds__(64) jac_wave_kernel(DevMech M, int64_t n, const double *y, int64_t ld,
-                                                      const double *p, double *jac) {
+                                                      const double *p, double *jac, int cv) {
     extern __shared__ double lds_raw[];
-    const Lds L = carve(lds_raw, M.nsp, true);
+    Lds L = carve(lds_raw, M.nsp, true);
+    L.cv = cv;
     init_lds(M, L);
     const int N = M.N, lane = lane_id();
     const int64_t r = xcd_reactor(blockIdx.x, int64_t(gridDim.x));
@@ -1039,6 +1066,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // compile-time constant, so LDS addresses need no scalar registers
     extern __shared__ double lds_raw[];
     Lds L = carve(lds_raw, S::NSMAX, S::JAC, S::WIN > 0 ? S::WIN : S::NSMAX);
+    L.cv = o.reactor;
     if (S::PARK) L.park = park + size_t(blockIdx.x) * (size_t(S::PARK_ROWS) * 64);
     init_lds(M, L);
     for (;;) {
@@ -1099,22 +1127,22 @@ size_t wave_ws_bytes(const DevMech &M, int cus) {
 }
 
 int launch_rhs_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
-                    hipStream_t s) {
+                    int cv, hipStream_t s) {
     const size_t lds = lds_doubles(M.nsp, false) * sizeof(double);
     const unsigned grid = unsigned((n + 7) / 8 * 8);
     if (M.N <= 64)
-        rhs_wave_kernel<1><<<dim3(grid), dim3(64), lds, s>>>(M, n, y, ld, p, dydt);
+        rhs_wave_kernel<1><<<dim3(grid), dim3(64), lds, s>>>(M, n, y, ld, p, dydt, cv);
     else
-        rhs_wave_kernel<2><<<dim3(grid), dim3(64), lds, s>>>(M, n, y, ld, p, dydt);
+        rhs_wave_kernel<2><<<dim3(grid), dim3(64), lds, s>>>(M, n, y, ld, p, dydt, cv);
     return hipGetLastError() == hipSuccess ? CK_OK : CK_EHIP;
 }
 
 int launch_jac_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
-                    hipStream_t s) {
+                    int cv, hipStream_t s) {
     if (M.N > 64) return CK_EUNSUPPORTED;
     const size_t lds = lds_doubles(M.nsp, true) * sizeof(double);
     const unsigned grid = unsigned((n + 7) / 8 * 8);
-    jac_wave_kernel<<<dim3(grid), dim3(64), lds, s>>>(M, n, y, ld, p, jac);
+    jac_wave_kernel<<<dim3(grid), dim3(64), lds, s>>>(M, n, y, ld, p, jac, cv);
     return hipGetLastError() == hipSuccess ? CK_OK : CK_EHIP;
 }
 

@@ -10,6 +10,7 @@ struct IntOpts {
     double rtol, atol, h0, h_fixed;
     int64_t max_steps;
     int32_t precision, refine_sweeps, blocks_per_cu, jacobian;
+    int32_t reactor;   // 0 constant pressure, 1 constant volume
 };
 
 // lane-per-reactor family (k_lane.hip)
@@ -26,9 +27,9 @@ int launch_integrate_lane(int method, const DevMech &M, int64_t n, double *y, in
 bool wave_supported(const DevMech &M, int method, int precision);
 size_t wave_ws_bytes(const DevMech &M, int cus);   // queue counter + parked LU rows
 int launch_rhs_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
-                    hipStream_t s);
+                    int cv, hipStream_t s);
 int launch_jac_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
-                    hipStream_t s);
+                    int cv, hipStream_t s);
 int launch_integrate_wave(int method, const DevMech &M, int64_t n, double *y, int64_t ld, const double *p,
                           const double *t_end, double *t, double *h, const IntOpts &o, void *ws,
                           int32_t *status, int32_t *nacc, int32_t *nrej, hipStream_t s);

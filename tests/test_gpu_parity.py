@@ -90,7 +90,7 @@ def _integrate_both(ck, g, om, y, P, t_end, method, kernel, **kw):
     res = ck.integrate(g, dev(y), dev(P), t_end, method=method, kernel=kernel, **kw)
     torch.cuda.synchronize()
     orc = om.integrate(y, P, t_end, method, **{k: v for k, v in kw.items() if k in ("rtol", "atol", "max_steps",
-                                                                                    "h0", "h_fixed", "jacobian")})
+                                                                                    "h0", "h_fixed", "jacobian", "reactor")})
     return {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in res.items()}, orc
 
 
@@ -237,3 +237,78 @@ def test_fd_jacobian_option_rejected_where_unsupported(ck, gmech):
         ck.integrate(g13, dev(y), dev(P), 1e-9, kernel="lane", jacobian="fd")
     with pytest.raises(ck.CkError):
         ck.integrate(g13, dev(y), dev(P), 1e-9, kernel="wave", jacobian="fd", precision="fp32_refine")
+
+
+# ---- constant-volume form (Section 3): fixed density, c_v and internal energies ----------------
+
+def _density(om, y, P):
+    S = (y[1:] / np.asarray(om.W)[:, None]).sum(axis=0)
+    return P / (synth.R_GAS * y[0] * S)
+
+
+@pytest.mark.parametrize("name,n", [("M13", 200), ("M53", 131), ("M111", 70)])
+def test_rhs_cv_parity(ck, gmech, oracle_mech, name, n):
+    g, om = gmech(name), oracle_mech(name)
+    y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=111)
+    rho = _density(om, y, P)
+    f = ck.rhs(g, dev(y), dev(rho), reactor="cv").cpu().numpy()
+    fo = om.rhs(y, rho, reactor="cv")
+    # the pressure of the same state gives the same concentrations, hence the same gross rates;
+    # the temperature row is scaled by sum_k |U_k| G_k / (rho c_v) instead
+    D = rhs_scale(om, y, P)
+    W = np.asarray(om.W)
+    nu = np.abs(om.stoich()).astype(float)
+    for r in range(n):
+        qf, qr, _, _, hRT = om.rates(y[:, r], P[r])
+        G = nu @ (np.abs(qf) + np.abs(qr))
+        cp, _, _ = om.thermo(y[0, r])
+        cv = (y[1:, r] * synth.R_GAS * (cp - 1.0) / W).sum()
+        U = synth.R_GAS * y[0, r] * (hRT - 1.0)
+        D[0, r] = np.sum(np.abs(U) * G) / (rho[r] * cv)
+    err = np.abs(f - fo) / D
+    print(f"[rhs cv {name}] max scaled error {err.max():.3e}", flush=True)
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("name,n", [("M13", 70), ("M53", 66)])
+def test_jacobian_cv_parity(ck, gmech, oracle_mech, name, n):
+    g, om = gmech(name), oracle_mech(name)
+    y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=212)
+    rho = _density(om, y, P)
+    J = ck.jac(g, dev(y), dev(rho), reactor="cv").cpu().numpy().T.reshape(n, om.N, om.N)
+    Jo = om.jac(y, rho, reactor="cv")
+    err = jac_scaled_error(J, Jo, y)
+    print(f"[jac cv {name}] max scaled error {err:.3e}", flush=True)
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("name,n,te", [("M13", 256, 1e-5), ("M53", 40, 1e-6)])
+def test_ros4_cv_parity(ck, gmech, oracle_mech, name, n, te):
+    g, om = gmech(name), oracle_mech(name)
+    y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=1011)
+    rho = _density(om, y, P)
+    res, orc = _integrate_both(ck, g, om, y, rho, te, "ros4", "wave", reactor="cv")
+    assert np.array_equal(res["status"], orc["status"])
+    _report_and_check(f"ros4 cv {name}", res, orc)
+
+
+def test_rkf45_cv_parity(ck, gmech, oracle_mech):
+    g, om = gmech("M13"), oracle_mech("M13")
+    y, P = synth.reactor_states(om.n_species, 128, "small", seed=1012)
+    rho = _density(om, y, P)
+    res, orc = _integrate_both(ck, g, om, y, rho, 2e-12, "rkf45", "wave", reactor="cv")
+    assert np.array_equal(res["status"], orc["status"])
+    _report_and_check("rkf45 cv M13", res, orc)
+
+
+def test_cv_rejected_where_unsupported(ck, gmech):
+    g = gmech("M13")
+    y, P = synth.reactor_states(g.n_species, 2, "small", seed=3)
+    with pytest.raises(ck.CkError):
+        ck.integrate(g, dev(y), dev(P), 1e-9, kernel="lane", reactor="cv")
+    with pytest.raises(ck.CkError):
+        ck.rhs(g, dev(y), dev(P), kernel="lane", reactor="cv")
+    g111 = gmech("M111")
+    y, P = synth.reactor_states(g111.n_species, 2, "divergent", seed=3)
+    with pytest.raises(ck.CkError):
+        ck.integrate(g111, dev(y), dev(P), 1e-9, reactor="cv")
