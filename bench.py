@@ -372,6 +372,15 @@ def main():
     torch.cuda.synchronize()
     rhs_s = e0.elapsed_time(e1) / 1e3
     rhs_rate = a.rhs_evals * a.reactors / rhs_s
+    # the same leg with one reactor per lane (shallow vectorisation, Section 4) for comparison
+    ck.rhs(g, batches[0], Pd, out=out, kernel="lane")
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(a.rhs_evals):
+        ck.rhs(g, batches[k % nb], Pd, out=out, kernel="lane")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    rhs_rate_lane = a.rhs_evals * a.reactors / (e0.elapsed_time(e1) / 1e3)
 
     res = {
         "metric": METRIC,
@@ -390,6 +399,7 @@ def main():
                    "mechanism": f"{a.mech} ({info['n_species']} species, {len(info['reactions'])} reactions)",
                    "reactors": a.reactors, "t_end": a.t_end, "kernel": a.kernel, "precision": a.precision},
         "rhs_evals_per_s": rhs_rate,
+        "rhs_evals_per_s_lane_kernel": rhs_rate_lane,
         "mean_steps_per_reactor": total_steps / a.reactors,
         "launches_per_step": launches,
         "status_counts": {"ok": status[0], "max_steps": status[1], "h_underflow": status[2], "nonfinite": status[3]},
