@@ -272,8 +272,8 @@ def suite_serving(a):
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: reactors are independent and this build runs on a single "
-              "MI355X; --gpus must be 1", file=sys.stderr)
+        print("bench.py measures one GPU: the reactors are independent and the library runs on a single "
+              "device, so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
