@@ -398,33 +398,23 @@ __device__ __forceinline__ double gj_apply(const double (&a)[NP], const Lds &L, 
     return x;
 }
 
-// Same product with the inverse read back from its parked copy (column j of the rotated row of
-// thread t at rows[j * 64 W + t]: consecutive threads read consecutive addresses).
-template <int W, int NP>
-__device__ __forceinline__ double gj_apply_parked(const Lds &L, int ord, double b) {
-    using G = Grp<W>;
-    const int tid = G::tid();
-    if (ord < NP) L.BS[ord] = b;
-    __syncthreads();
-    double s = 0.0;
-    if (ord < NP) {
-        const double *r = L.rows + tid;
-#pragma unroll 8
-        for (int j = 0; j < NP; j++) s = fma(r[j * G::T], L.BS[j], s);
-        L.XS[ord] = s;
-    }
-    __syncthreads();
-    const double x = tid < NP ? L.XS[tid] : 0.0;
-    __syncthreads();
-    return x;
-}
-
 template <int W, int NP, int NWIN, int WIN, bool PARK>
 struct Ros4Coop {
     static constexpr double qinv = 0.25;
     static constexpr size_t kRows = size_t(NP) * 64 * W;   // parked doubles per workgroup
-    __device__ static __forceinline__ double apply(const double (&a)[NP], const Lds &L, int ord, double b) {
-        return PARK ? gj_apply_parked<W, NP>(L, ord, b) : gj_apply<W, NP>(a, L, ord, b);
+    // the inverse rows go to the workspace while the stage source terms are evaluated and come
+    // back as one batch of independent loads before the next products
+    __device__ static __forceinline__ void park(const Lds &L, const double (&a)[NP]) {
+        if (!PARK) return;
+        double *r = L.rows + opaque(Grp<W>::tid());
+#pragma unroll
+        for (int j = 0; j < NP; j++) r[j * Grp<W>::T] = a[j];
+    }
+    __device__ static __forceinline__ void unpark(const Lds &L, double (&a)[NP]) {
+        if (!PARK) return;
+        const double *r = L.rows + opaque(Grp<W>::tid());
+#pragma unroll
+        for (int j = 0; j < NP; j++) a[j] = r[j * Grp<W>::T];
     }
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
                                 double &e) {
@@ -434,18 +424,16 @@ struct Ros4Coop {
         iteration_rows<W, NP, NWIN, WIN>(M, L, y, P, dg, a, f);
         int ord;
         const bool ok = gj_invert<W, NP>(a, L, ord);
-        if (PARK && ord < NP) {
-            double *r = L.rows + Grp<W>::tid();
-#pragma unroll
-            for (int j = 0; j < NP; j++) r[j * Grp<W>::T] = a[j];
-        }
         const double ih = 1.0 / h;
-        const double u1 = apply(a, L, ord, f);
+        const double u1 = gj_apply<W, NP>(a, L, ord, f);
+        park(L, a);
         double ft = rhs<W>(M, L, y + Ros4::a21 * u1, P);
-        const double u2 = apply(a, L, ord, ft + (Ros4::c21 * u1) * ih);
+        unpark(L, a);
+        const double u2 = gj_apply<W, NP>(a, L, ord, ft + (Ros4::c21 * u1) * ih);
         ft = rhs<W>(M, L, y + Ros4::a31 * u1 + Ros4::a32 * u2, P);
-        const double u3 = apply(a, L, ord, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
-        const double u4 = apply(a, L, ord, ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
+        unpark(L, a);
+        const double u3 = gj_apply<W, NP>(a, L, ord, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
+        const double u4 = gj_apply<W, NP>(a, L, ord, ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
         ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
         e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
         return ok;
