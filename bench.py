@@ -34,11 +34,11 @@ PEAK_FP64_VECTOR = 78.6e12
 TRAFFIC_REF = {
     "sources": ["paper_1608_05794_amd/csrc/k_wave.hip", "paper_1608_05794_amd/csrc/kinetics.h",
                 "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h"],
-    "sha256": "af2a157932cedf005fb67ade32453b93340c46a19849a508dc3c0713fadc7bc4",
+    "sha256": "4431395554c579c0a120ee3908ea12a6a56b87820f309a2ce153f4891d043bd0",
     "args": {"mech": "M53", "reactors": 131072, "t_end": 1e-3, "kernel": "wave", "precision": "fp64",
              "launch_steps": 2000},
-    "fetch_kib_per_launch": 3772271907.0, "fetch_factor": 1048576.0 / 524302.3,
-    "write_kib_per_launch": 5489005747.5, "write_factor": 1.0,
+    "fetch_kib_per_launch": 3765407590.3, "fetch_factor": 1048576.0 / 524303.75,
+    "write_kib_per_launch": 5488711913.25, "write_factor": 1.0,
 }          # FLOP/s, MI355X FP64 vector (VALU)
 TRANSCENDENTAL_FLOPS = 20           # FP64 operations charged per exp / log / log10 / exp10
 
