@@ -199,6 +199,15 @@ def suite_batching(a):
             print(f"batching {mech} {k}: {done / dt / 1e6:.3f} M reactor-steps/s", file=sys.stderr, flush=True)
         row["speedup"] = row[kernels[0]]["reactor_steps_per_s"] / row[kernels[1]]["reactor_steps_per_s"]
         out[f"{mech}_x{n}_{steps}_steps"] = row
+    # launch configuration chosen by the autotuner on a 16384-reactor sample of each workload
+    from paper_1608_05794_amd import tune
+    for mech, seed in (("M53", 1002), ("M111", 1003)):
+        g = ck.Mechanism(synth.mechanism_file(mech))
+        y, P = _states(synth, torch, mech, 16384, seed)
+        best, table = tune.tune(g, y, P, 1e-3, steps=12)
+        out[f"autotune_{mech}"] = {"best": {k: best[k] for k in ("kernel", "blocks_per_cu")},
+                                   "table": [[c["kernel"], c["blocks_per_cu"], v] for c, v in table]}
+        print(f"autotune {mech}: {best}", file=sys.stderr, flush=True)
     # waste of lockstep groups (Eq. waste) from complete integrations of a 111-species sample
     g = ck.Mechanism(synth.mechanism_file("M111"))
     y, P = _states(synth, torch, "M111", 2048, 1003)

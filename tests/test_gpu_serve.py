@@ -53,3 +53,18 @@ def test_admission_respects_budget(mech_path):
     finally:
         serve.Pool.admit = orig
     assert len(done) == 6 and max(peak) <= 2
+
+
+def test_autotuner_returns_a_working_configuration(mech_path):
+    from paper_1608_05794_amd import ck, tune
+    g = ck.Mechanism(mech_path("M13"))
+    y0, P = synth.reactor_states(g.n_species, 512, "small", seed=5)
+    y, p = torch.as_tensor(y0, device="cuda"), torch.as_tensor(P, device="cuda")
+    best, table = tune.tune(g, y, p, 1e-6, steps=5)
+    assert table and all(v > 0 for _, v in table)
+    assert best["kernel"] in ("wave", "group", "lane")
+    # the chosen options integrate to the same result as the default launch (kernel choice aside)
+    r = ck.integrate(g, y, p, 1e-7, **best)
+    torch.cuda.synchronize()
+    assert np.all(r["status"].cpu().numpy() == 0)
+    assert np.array_equal(y.cpu().numpy(), y0)   # the tuner leaves the sample untouched

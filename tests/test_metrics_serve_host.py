@@ -35,3 +35,13 @@ def test_slot_bookkeeping():
     assert p.free == [(0, 30), (80, 100)]
     p.release(*b)
     assert p.free == [(0, 100)]
+
+
+def test_tuner_candidates():
+    from paper_1608_05794_amd import tune
+    c53 = tune.candidates(54)
+    assert {"kernel": "wave", "blocks_per_cu": 8} in c53 and {"kernel": "lane", "blocks_per_cu": 0} in c53
+    c112 = tune.candidates(112)
+    assert all(c["kernel"] != "wave" for c in c112) and any(c["kernel"] == "group" for c in c112)
+    assert all(c["kernel"] == "wave" for c in tune.candidates(54, precision="fp32_refine"))
+    assert tune.candidates(200) == [{"kernel": "lane", "blocks_per_cu": 0}]
