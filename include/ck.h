@@ -55,8 +55,9 @@ enum {
     CK_KERNEL_AUTO = 0,    /* ROS4: WAVE if N <= 64, else GROUP if N <= 128; RKF45: WAVE if N <= 128 */
     CK_KERNEL_LANE = 1,    /* one reactor per lane, all scratch in global memory (Algorithm 2 analogue) */
     CK_KERNEL_WAVE = 2,    /* one reactor per 64-lane wavefront, persistent work queue, LU in registers */
-    CK_KERNEL_GROUP = 3    /* ROS4 only: one reactor per workgroup of 1 (N <= 64) or 2 (N <= 128)
-                              wavefronts, persistent work queue, Gauss-Jordan inverse in registers */
+    CK_KERNEL_GROUP = 3    /* ROS4 only: one reactor per workgroup of 1 (N <= 64) or 4 (N <= 128, matrix
+                              rows split over thread pairs) wavefronts, persistent work queue,
+                              Gauss-Jordan inverse in registers */
 };
 
 /* Reactor form (Section 3).  Constant pressure: p[] holds pressures (Pa); the density follows

@@ -1,27 +1,27 @@
-// Workgroup-cooperative ROS4: W wavefronts (64 W threads) own one reactor.
-//   - thread t holds state component t (T on thread 0, Y_{t-1} on thread t);
-//   - source term and Jacobian as in the wavefront kernels (species phases
-//     thread-per-species, reaction phases thread-per-reaction with LDS FP64
-//     atomics), with group-wide reductions and broadcasts through LDS when W > 1;
-//   - for W = 2 the Jacobian's d wdot/dC is staged in LDS in two column
-//     windows, so two reactors fit in one CU's LDS;
-//   - the iteration matrix M = I/(gamma h) - J lives in registers, one row per
-//     thread, and is inverted in place by Gauss-Jordan elimination with partial
-//     pivoting.  Each elimination step rotates the row left by one, so the
-//     pivot column is always register 0 and the loop body is the same code for
-//     every step (a runtime loop, small code).  The four stage solves of a
-//     step are then matrix-vector products with no sequential substitution.
-//   - with two wavefronts (N > 64) a thread's row of the inverse (up to 128
-//     doubles) is parked in a per-workgroup slice of the workspace while the
-//     stage right-hand sides are evaluated, so the source-term code does not
-//     have to share the register file with it.
+// Workgroup-cooperative ROS4: one reactor per workgroup.
+//   - thread t holds state component t (T on thread 0, Y_{t-1} on thread t)
+//     in the source-term phases: species phases thread-per-species, reaction
+//     phases thread-per-reaction with LDS FP64 atomics, group-wide reductions
+//     and broadcasts through LDS;
+//   - the iteration matrix M = I/(gamma h) - J lives in registers and is
+//     inverted in place by Gauss-Jordan elimination with partial pivoting.
+//     Each elimination step rotates the rows left by one, so the pivot column
+//     is always register 0 and one loop body serves every step.  The four
+//     stage solves of a step are then matrix-vector products with no
+//     sequential substitution;
+//   - N <= 64: one wavefront, one matrix row per thread;
+//   - N > 64: four wavefronts, each row split over a pair of adjacent threads
+//     (half rows of N'/2 doubles), d wdot/dC staged in LDS in two column
+//     windows (one per half), so two reactors fit in one CU's LDS and two
+//     wavefronts fit each SIMD.  The inverse is parked in a per-workgroup
+//     slice of the workspace while the stage right-hand sides are evaluated.
 // Reactors come from the same device work queue as the wavefront kernels.
 #include "ck_internal.h"
 #include "kinetics.h"
 #include "launch.h"
 
 extern "C" __device__ unsigned long long __ockl_wfred_max_u64(unsigned long long);
-extern "C" __device__ __forceinline__ double __ockl_wfred_add_f64(double);
+extern "C" __device__ double __ockl_wfred_add_f64(double);
 
 namespace ck {
 namespace coop {
@@ -43,16 +43,19 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
 struct Lds {
     double *C, *G, *H, *WD, *IW, *VX, *RED, *PB, *BS, *XS, *JC, *TB, *DWT, *TROW;
     double *rows;   // parked inverse of this workgroup ([NP][64 W], global memory), or null
+    // half-row kernel only: per-row chain-rule scalars and pivot orders, [128] each
+    double *RA, *RB, *RC, *RJ;
+    int *ORD;
     int ldj;
 };
 
 __host__ __device__ inline int ldj_of(int win) { return win | 1; }
-__host__ __device__ inline size_t lds_doubles(int ns, int win) {
+__host__ __device__ inline size_t lds_doubles(int ns, int win, bool half = false) {
     return size_t(ns + 1) + 3 * size_t(ns) + 128 + 128 + 16 + 2 * 128 + 128 + 128 + size_t(ns) * ldj_of(win) + 128 +
-           2 * size_t(ns) + size_t(ns) + 128;
+           2 * size_t(ns) + size_t(ns) + 128 + (half ? 4 * 128 + 64 : 0);
 }
 
-__device__ __forceinline__ Lds carve(double *b, int ns, int win) {
+__device__ __forceinline__ Lds carve(double *b, int ns, int win, bool half = false) {
     Lds L;
     L.ldj = ldj_of(win);
     L.C = b; b += ns + 1;
@@ -68,8 +71,17 @@ __device__ __forceinline__ Lds carve(double *b, int ns, int win) {
     L.JC = b; b += size_t(ns) * L.ldj + 128;
     L.TB = b; b += ns;
     L.DWT = b; b += ns;
-    L.TROW = b;
+    L.TROW = b; b += ns + 128;
     L.rows = nullptr;
+    L.RA = L.RB = L.RC = L.RJ = nullptr;
+    L.ORD = nullptr;
+    if (half) {
+        L.RA = b; b += 128;
+        L.RB = b; b += 128;
+        L.RC = b; b += 128;
+        L.RJ = b; b += 128;
+        L.ORD = reinterpret_cast<int *>(b);
+    }
     return L;
 }
 
@@ -402,6 +414,7 @@ template <int W, int NP, int NWIN, int WIN, bool PARK>
 struct Ros4Coop {
     static constexpr double qinv = 0.25;
     static constexpr size_t kRows = size_t(NP) * 64 * W;   // parked doubles per workgroup
+    static constexpr bool kHalf = false;
     // the inverse rows go to the workspace while the stage source terms are evaluated and come
     // back as one batch of independent loads before the next products
     __device__ static __forceinline__ void park(const Lds &L, const double (&a)[NP]) {
@@ -434,6 +447,211 @@ struct Ros4Coop {
         unpark(L, a);
         const double u3 = gj_apply<W, NP>(a, L, ord, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
         const double u4 = gj_apply<W, NP>(a, L, ord, ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
+        ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
+        e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
+        return ok;
+    }
+};
+
+// ---------------------------------------------------------------------------------------
+// Half-row variant (N > 64): four wavefronts per reactor; row r of the iteration matrix is split
+// over threads 2r (matrix columns [0, H)) and 2r + 1 (columns [H, 2H)), H = NP / 2, so a thread
+// holds H doubles, leaving registers to batch the pivot-row reads and room for two wavefronts
+// per SIMD.  Source-term phases keep the component mapping of the other kernels (thread i holds
+// state component i); per-row scalars and pivot orders pass between the mappings through LDS.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double shfl_pair(double v) { return __shfl_xor(v, 1); }   // partner (lane ^ 1)
+
+template <int NP>
+__device__ __forceinline__ void iteration_rows_half(const DevMech &M, const Lds &L, double y, double P, double dg,
+                                                    double (&a)[NP / 2], double &f) {
+    constexpr int W = 4, H = NP / 2;
+    using G = Grp<W>;
+    const int ns = M.nsp;
+    Mix x;
+    species_pass<W, true>(M, y, P, L, x);
+    const int tid = G::tid();
+    const int k = species_of(tid, ns);              // component mapping
+    const bool valid = k >= 0;
+    const int row = tid >> 1, half = tid & 1;       // row mapping
+    const int kr = row - 1;                         // species of the row (row 0 is T)
+    const bool rvalid = row >= 1 && row <= ns;
+    double colH = 0.0, jcp = 0.0;                   // jcp: this half's part of sum_l JC[kr][l] C_l
+#pragma unroll
+    for (int j = 0; j < H; j++) a[j] = 0.0;
+#pragma unroll
+    for (int w = 0; w < 2; w++) {
+        const int c0 = w * H - 1;                   // window w: matrix columns [w H, w H + H)
+        reaction_pass<W, true>(M, L, x.t, x.Ctot, c0, H, w == 0);
+        if (w == 0) f = finish_rhs<W>(M, L, x);
+        if (rvalid && half == w) {
+            const double *r = &L.JC[kr * L.ldj];
+#pragma unroll
+            for (int j = 0; j < H; j++) {
+                const int jc = c0 + j;              // JC column of matrix column w H + j
+                if (jc >= 0 && jc < ns) {
+                    const double v = r[j];
+                    a[j] = v;                       // raw d wdot_kr / dC_jc until the row scalars are known
+                    jcp += v * L.C[jc];
+                }
+            }
+        }
+        if (valid && k + 1 >= w * H && k + 1 < w * H + H)
+            for (int r = 0; r < ns; r++) colH += L.H[r] * L.JC[r * L.ldj + (k + 1 - w * H)];
+        __syncthreads();
+    }
+    const double jrow = jcp + shfl_pair(jcp);
+    if (half == 0 && rvalid) L.RJ[row] = jrow;
+    __syncthreads();
+    // chain rule in the component mapping (as iteration_rows)
+    const double T = x.t.T, RT = M.R * T;
+    double jcc = 0.0, resid = 0.0, ra = 0.0, col0 = 0.0, TBk = 0.0, WDk = 0.0, DWTk = 0.0;
+    if (valid) {
+        TBk = L.TB[k];
+        WDk = L.WD[k];
+        DWTk = L.DWT[k];
+        jcc = L.RJ[tid] + TBk * x.Ctot;
+        colH *= RT;
+        resid = WDk - jcc;
+        ra = M.W()[k] * x.Wbar * resid / x.rho;
+        col0 = (M.W()[k] / x.rho) * (DWTk + resid * x.t.invT);
+    }
+    const double Hk = RT * x.h;
+    const double sumHTB = G::sum(valid ? Hk * TBk : 0.0, L.RED);
+    const double sumHJCC = G::sum(valid ? Hk * jcc : 0.0, L.RED);
+    const double dQT = G::sum(valid ? M.R * x.cp * WDk + Hk * (DWTk - jcc * x.t.invT) : 0.0, L.RED);
+    const double sdcp = G::sum(valid ? y * M.R * x.dcp * M.invW()[k] : 0.0, L.RED);
+    const double fT = G::bcast(f, 0, L.RED + 8);
+    const double D = x.rho * x.cpm;
+    if (valid) {
+        const double dQ = M.invW()[k] * (x.rho * (colH + sumHTB) - x.Wbar * sumHJCC);
+        const double dD = x.rho * M.invW()[k] * (M.R * x.cp - x.cpm * x.Wbar);
+        L.TROW[k] = -(dQ + fT * dD) / D;
+    }
+    if (tid < 128) {
+        L.RA[tid] = valid ? M.W()[k] : 0.0;
+        L.RB[tid] = valid ? M.W()[k] * TBk + ra : 0.0;
+        L.RC[tid] = valid ? col0 : 0.0;
+    }
+    const double J00 = -(dQT + fT * (-x.rho * x.cpm * x.t.invT + x.rho * sdcp)) / D;
+    __syncthreads();
+    const double alpha = row < 128 ? L.RA[row] : 0.0;
+    const double beta = row < 128 ? L.RB[row] : 0.0;
+    const double c0r = row < 128 ? L.RC[row] : 0.0;
+#pragma unroll
+    for (int j = 0; j < H; j++) {
+        const int c = half * H + j;                 // matrix column
+        double v;
+        if (c == 0) {
+            v = (row == 0 ? dg : 0.0) - (row == 0 ? J00 : c0r);
+        } else {
+            const double Jv = row == 0 ? L.TROW[c - 1] : L.IW[c - 1] * (alpha * a[j] + beta);
+            v = (row == c ? dg : 0.0) - Jv;
+        }
+        a[j] = v;
+    }
+    __syncthreads();
+}
+
+// Gauss-Jordan inverse on half rows (rotated as gj_invert): the pivot-column entry of a row is
+// element 0 of its first half; each step shifts both halves left by one, the first half taking
+// the partner's element 0.  On return ORD[r] is the pivot order of row r.
+template <int NP>
+__device__ __forceinline__ bool gj_invert_half(double (&a)[NP / 2], const Lds &L, int &ord) {
+    constexpr int W = 4, H = NP / 2;
+    using G = Grp<W>;
+    const int tid = G::tid();
+    const int row = tid >> 1, half = tid & 1;
+    bool done = row >= NP;
+    bool ok = true;
+    ord = NP;
+    for (int k = 0; k < NP; k++) {
+        const double p0 = shfl_pair(a[0]);          // partner's element 0
+        const double f = half ? p0 : a[0];          // the row's entry in the pivot column
+        const unsigned long long key =
+            (done || half) ? 0ull : (unsigned long long)__double_as_longlong(fabs(f));
+        unsigned long long best;
+        const int p = G::argmax(key, L.RED, best) >> 1;
+        ok = ok && best != 0ull;
+        double *buf = L.PB + (k & 1) * 128;
+        if (row == p) {
+            const double r = 1.0 / f;
+#pragma unroll
+            for (int j = 0; j < H - 1; j++) a[j] = a[j + 1] * r;
+            a[H - 1] = (half ? 1.0 : p0) * r;
+#pragma unroll
+            for (int j = 0; j < H; j++) buf[half * H + j] = a[j];
+            done = true;
+            ord = k;
+        }
+        __syncthreads();
+        if (row != p) {
+            const double *pb = buf + half * H;
+#pragma unroll
+            for (int j = 0; j < H - 1; j++) a[j] = fma(-f, pb[j], a[j + 1]);
+            a[H - 1] = half ? -f * pb[H - 1] : fma(-f, pb[H - 1], p0);
+        }
+    }
+    if (half == 0 && row < NP) L.ORD[row] = ord;
+    __syncthreads();
+    return ok;
+}
+
+// x = M^-1 b with the half-row rotated inverse; b and x in the component mapping.
+template <int NP>
+__device__ __forceinline__ double gj_apply_half(const double (&a)[NP / 2], const Lds &L, int ord, double b) {
+    constexpr int W = 4, H = NP / 2;
+    using G = Grp<W>;
+    const int tid = G::tid();
+    const int row = tid >> 1, half = tid & 1;
+    if (tid < NP && L.ORD[tid] < NP) L.BS[L.ORD[tid]] = b;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < H; j++) s = fma(a[j], L.BS[half * H + j], s);
+    s += shfl_pair(s);
+    if (half == 0 && row < NP && ord < NP) L.XS[ord] = s;
+    __syncthreads();
+    const double x = tid < NP ? L.XS[tid] : 0.0;
+    __syncthreads();
+    return x;
+}
+
+template <int NP>
+struct Ros4CoopHalf {
+    static constexpr double qinv = 0.25;
+    static constexpr int H = NP / 2;
+    static constexpr bool kHalf = true;
+    static constexpr size_t kRows = size_t(H) * 256;   // parked doubles per workgroup
+    __device__ static __forceinline__ void park(const Lds &L, const double (&a)[H]) {
+        double *r = L.rows + opaque(Grp<4>::tid());
+#pragma unroll
+        for (int j = 0; j < H; j++) r[j * 256] = a[j];
+    }
+    __device__ static __forceinline__ void unpark(const Lds &L, double (&a)[H]) {
+        const double *r = L.rows + opaque(Grp<4>::tid());
+#pragma unroll
+        for (int j = 0; j < H; j++) a[j] = r[j * 256];
+    }
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h,
+                                                double &ynew, double &e) {
+        double a[H];
+        double f;
+        const double dg = 1.0 / (Ros4::gamma * h);
+        iteration_rows_half<NP>(M, L, y, P, dg, a, f);
+        int ord;
+        const bool ok = gj_invert_half<NP>(a, L, ord);
+        const double ih = 1.0 / h;
+        const double u1 = gj_apply_half<NP>(a, L, ord, f);
+        park(L, a);
+        double ft = rhs<4>(M, L, y + Ros4::a21 * u1, P);
+        unpark(L, a);
+        const double u2 = gj_apply_half<NP>(a, L, ord, ft + (Ros4::c21 * u1) * ih);
+        ft = rhs<4>(M, L, y + Ros4::a31 * u1 + Ros4::a32 * u2, P);
+        unpark(L, a);
+        const double u3 = gj_apply_half<NP>(a, L, ord, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
+        const double u4 =
+            gj_apply_half<NP>(a, L, ord, ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
         ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
         e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
         return ok;
@@ -539,7 +757,7 @@ __global__ void __launch_bounds__(64 * W) coop_kernel(DevMech M, int64_t n, doub
                                                       unsigned *queue, double *park, int32_t *status,
                                                       int32_t *nacc, int32_t *nrej) {
     extern __shared__ double lds_raw[];
-    Lds L = carve(lds_raw, M.nsp, WIN);
+    Lds L = carve(lds_raw, M.nsp, WIN, S::kHalf);
     if (park) L.rows = park + size_t(blockIdx.x) * S::kRows;
     init_lds(M, L, int(threadIdx.x), 64 * W);
     __shared__ int64_t next;
@@ -559,13 +777,11 @@ __global__ void zero_queue_kernel(unsigned *q) { *q = 0u; }
 // Workgroups per CU of a parking kernel are capped so that the parked rows fit the workspace.
 constexpr int kParkBlocksPerCu = 2;
 
-template <int W, int NP, int NWIN, int WIN>
-int launch(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end, double *t,
-           double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc, int32_t *nrej,
-           hipStream_t s) {
-    constexpr bool PARK = W > 1;
-    using S = Ros4Coop<W, NP, NWIN, WIN, PARK>;
-    const size_t lds = lds_doubles(M.nsp, WIN) * sizeof(double);
+template <int W, class S, int WIN, bool PARK>
+int launch_kernel(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end, double *t,
+                  double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc, int32_t *nrej,
+                  hipStream_t s) {
+    const size_t lds = lds_doubles(M.nsp, WIN, S::kHalf) * sizeof(double);
     auto kern = coop_kernel<W, S, WIN>;
     if (lds > 64 * 1024 && hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
@@ -586,6 +802,23 @@ int launch(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, 
     return hipGetLastError() == hipSuccess ? CK_OK : CK_EHIP;
 }
 
+template <int W, int NP, int NWIN, int WIN>
+int launch(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end, double *t,
+           double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc, int32_t *nrej,
+           hipStream_t s) {
+    constexpr bool PARK = W > 1;
+    return launch_kernel<W, Ros4Coop<W, NP, NWIN, WIN, PARK>, WIN, PARK>(M, n, y, ld, p, t_end, t, h, o, queue,
+                                                                         status, nacc, nrej, s);
+}
+
+template <int NP>
+int launch_half(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end, double *t,
+                double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc, int32_t *nrej,
+                hipStream_t s) {
+    return launch_kernel<4, Ros4CoopHalf<NP>, NP / 2, true>(M, n, y, ld, p, t_end, t, h, o, queue, status, nacc,
+                                                            nrej, s);
+}
+
 }  // namespace coop
 
 bool coop_supported(const DevMech &M) { return M.N <= 128; }
@@ -604,7 +837,7 @@ int launch_integrate_coop(const DevMech &M, int64_t n, double *y, int64_t ld, co
 #define CK_COOP1(NPV) \
     case NPV: return coop::launch<1, NPV, 1, NPV>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
 #define CK_COOP2(NPV) \
-    case NPV: return coop::launch<2, NPV, 2, NPV / 2>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+    case NPV: return coop::launch_half<NPV>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
     switch (np) {
         CK_COOP1(8) CK_COOP1(16) CK_COOP1(24) CK_COOP1(32) CK_COOP1(40) CK_COOP1(48) CK_COOP1(56) CK_COOP1(64)
         CK_COOP2(72) CK_COOP2(80) CK_COOP2(88) CK_COOP2(96) CK_COOP2(104) CK_COOP2(112) CK_COOP2(120)
