@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "reactors/s integrated (ROS4, rtol 1e-8), RHS evals/s, p50/p99 solve latency"
 KERNEL_NAMES = {"wave": "integrate_wave_kernel<Ros4Adapter>", "auto": "integrate_wave_kernel<Ros4Adapter>",
                 "group": "coop_kernel<Ros4Coop>", "lane": "integrate_lane_kernel<0>"}
-PEAK_FP64_VECTOR = 78.6e12
+PEAK_FP64_VECTOR = 78.6e12         # FLOP/s, MI355X FP64 vector (VALU)
 # HBM traffic of the integrator kernel from two rocprofv3 --pmc runs of the default command (one
 # with FETCH_SIZE, one with WRITE_SIZE; KiB per dispatch averaged over its launches), each scaled
 # by what the counter reads for a device-to-device copy of 1 GiB (FETCH_SIZE reads half the bytes,
@@ -34,12 +34,12 @@ PEAK_FP64_VECTOR = 78.6e12
 TRAFFIC_REF = {
     "sources": ["paper_1608_05794_amd/csrc/k_wave.hip", "paper_1608_05794_amd/csrc/kinetics.h",
                 "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h"],
-    "sha256": "4431395554c579c0a120ee3908ea12a6a56b87820f309a2ce153f4891d043bd0",
+    "sha256": "1c11169cc564b2e6627acb35b633d5c332b8e3f174332e2b6f3b101ccd75fed2",
     "args": {"mech": "M53", "reactors": 131072, "t_end": 1e-3, "kernel": "wave", "precision": "fp64",
              "launch_steps": 2000},
     "fetch_kib_per_launch": 3765407590.3, "fetch_factor": 1048576.0 / 524303.75,
     "write_kib_per_launch": 5488711913.25, "write_factor": 1.0,
-}          # FLOP/s, MI355X FP64 vector (VALU)
+}
 TRANSCENDENTAL_FLOPS = 20           # FP64 operations charged per exp / log / log10 / exp10
 
 

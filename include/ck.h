@@ -17,8 +17,12 @@
  *     null stream).  Calls are asynchronous on that stream; the return code
  *     covers argument validation and kernel launch only.
  *   - Return codes: CK_OK or a negative CK_E* value (see ck_strerror).
- *   - A mechanism handle is immutable after ck_mechanism_load and may be
- *     used from several streams at once.
+ *   - A mechanism handle's tables are immutable after ck_mechanism_load; the
+ *     handle may be used from several host threads and streams at once.
+ *     Calls that pass no workspace use a library-owned buffer per (mechanism,
+ *     stream), so concurrent calls on different streams never share one;
+ *     calls on one stream run in stream order.  A caller-supplied workspace
+ *     must not be in use by another call that may overlap in time.
  */
 #ifndef CK_H
 #define CK_H
@@ -57,7 +61,11 @@ enum {
     CK_KERNEL_WAVE = 2,    /* one reactor per 64-lane wavefront, persistent work queue, LU in registers */
     CK_KERNEL_GROUP = 3    /* ROS4 only: one reactor per workgroup of 1 (N <= 64) or 4 (N <= 128, matrix
                               rows split over thread pairs) wavefronts, persistent work queue,
-                              Gauss-Jordan inverse in registers */
+                              Gauss-Jordan inverse in registers.  With 4 wavefronts the reaction
+                              contributions are summed with LDS atomics in an order that varies
+                              between runs: results agree to rounding, not bit for bit.  Every other
+                              kernel gives bitwise identical results for identical inputs, whatever
+                              the batch a reactor is in */
 };
 
 /* Reactor form (Section 3).  Constant pressure: p[] holds pressures (Pa); the density follows
@@ -138,7 +146,9 @@ int ck_jacobian_eval(const ck_mech *m, int64_t n, const double *y, int64_t ld, c
 /*
  * Bytes of device workspace that ck_integrate_* needs for n reactors with
  * options o (NULL = defaults).  Pass a buffer at least this large as
- * `workspace`, or NULL to let the library allocate (and cache) its own.
+ * `workspace`, or NULL to let the library allocate its own: one per stream
+ * the mechanism is called on, kept (and grown when a call needs more, which
+ * waits for the device) until ck_mechanism_free.
  * Lane kernel: per-reactor scratch, linear in n.  Wavefront kernel: a
  * 256-byte queue counter.  Workgroup kernel with N > 64: the counter plus
  * the parked Gauss-Jordan inverses of the resident workgroups (2 per compute

@@ -3,7 +3,6 @@
 // k_wave.hip and k_coop.hip.
 #include <climits>
 #include <cmath>
-#include <mutex>
 
 #include "ck_internal.h"
 #include "launch.h"
@@ -24,22 +23,29 @@ struct DeviceGuard {
     }
 };
 
-std::mutex g_ws_mutex;
-
-// Library-owned workspace of a mechanism (used when the caller passes none).
-int cached_ws(ck_mech *m, size_t bytes, void **out) {
-    std::lock_guard<std::mutex> lk(g_ws_mutex);
-    if (m->ws_bytes < bytes) {
-        if (m->ws) {
-            hipDeviceSynchronize();
-            hipFree(m->ws);
-            m->ws = nullptr;
-            m->ws_bytes = 0;
-        }
-        if (hipMalloc(&m->ws, bytes) != hipSuccess) return CK_ENOMEM;
-        m->ws_bytes = bytes;
+// Library-owned workspace of a mechanism for calls on `s` that pass none.  Each stream gets its
+// own buffer: two streams running the persistent kernels at once must not share a queue counter.
+// Growing a buffer waits for the device before freeing the old one.
+int cached_ws(ck_mech *m, hipStream_t s, size_t bytes, void **out) {
+    std::lock_guard<std::mutex> lk(m->ws_mutex);
+    ck_mech::StreamWs *e = nullptr;
+    for (auto &w : m->ws)
+        if (w.stream == s) e = &w;
+    if (!e) {
+        m->ws.push_back({s, nullptr, 0});
+        e = &m->ws.back();
     }
-    *out = m->ws;
+    if (e->bytes < bytes) {
+        if (e->ptr) {
+            hipDeviceSynchronize();
+            hipFree(e->ptr);
+            e->ptr = nullptr;
+            e->bytes = 0;
+        }
+        if (hipMalloc(&e->ptr, bytes) != hipSuccess) return CK_ENOMEM;
+        e->bytes = bytes;
+    }
+    *out = e->ptr;
     return CK_OK;
 }
 
@@ -130,7 +136,7 @@ int integrate(int method, const ck_mech *mc, int64_t n, double *y, int64_t ld, c
     const size_t need = ck_workspace_bytes(m, n, o);
     void *ws = workspace;
     if (!ws) {
-        rc = cached_ws(m, need, &ws);
+        rc = cached_ws(m, s, need, &ws);
         if (rc != CK_OK) return rc;
     }
     if (kern == CK_KERNEL_WAVE)
@@ -185,7 +191,7 @@ extern "C" int ck_rhs_eval_ex(const ck_mech *mc, int64_t n, const double *y, int
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (kernel == CK_KERNEL_LANE) {
         void *ws = nullptr;
-        int rc = cached_ws(m, lane_bytes(m, n, 0), &ws);
+        int rc = cached_ws(m, s, lane_bytes(m, n, 0), &ws);
         if (rc != CK_OK) return rc;
         return launch_rhs_lane(m->dev, n, y, ld, p, dydt, static_cast<double *>(ws), round_up(n, 64), s);
     }
@@ -213,7 +219,7 @@ extern "C" int ck_jacobian_eval_ex(const ck_mech *mc, int64_t n, const double *y
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (kernel == CK_KERNEL_WAVE) return launch_jac_wave(m->dev, n, y, ld, p, jac, reactor, s);
     void *ws = nullptr;
-    int rc = cached_ws(m, lane_bytes(m, n, 0), &ws);
+    int rc = cached_ws(m, s, lane_bytes(m, n, 0), &ws);
     if (rc != CK_OK) return rc;
     return launch_jac_lane(m->dev, n, y, ld, p, jac, static_cast<double *>(ws), round_up(n, 64), s);
 }

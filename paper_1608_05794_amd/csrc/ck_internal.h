@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ck.h"
@@ -101,9 +102,16 @@ struct ck_mech {
     ck::DevMech dev{};
     void *dev_block = nullptr;      // single device allocation holding every table
     size_t dev_bytes = 0;
-    // workspace cache for calls that pass workspace == NULL
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
+    // Library-owned workspaces for calls that pass workspace == NULL: one per stream, so
+    // calls on different streams never share a queue counter or parking area (calls on one
+    // stream are ordered by the stream).  Guarded by ws_mutex; freed by ck_mechanism_free.
+    struct StreamWs {
+        hipStream_t stream;
+        void *ptr;
+        size_t bytes;
+    };
+    std::mutex ws_mutex;
+    std::vector<StreamWs> ws;
 };
 
 #define CK_HIP_TRY(expr)                       \

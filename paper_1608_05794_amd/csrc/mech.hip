@@ -293,7 +293,8 @@ extern "C" void ck_mechanism_free(ck_mech *m) {
     hipGetDevice(&prev);
     hipSetDevice(m->device);
     if (m->dev_block) hipFree(m->dev_block);
-    if (m->ws) hipFree(m->ws);
+    for (auto &w : m->ws)
+        if (w.ptr) hipFree(w.ptr);
     hipSetDevice(prev);
     delete m;
 }

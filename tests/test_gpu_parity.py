@@ -150,7 +150,7 @@ def test_ros4_m111_lane(ck, gmech, oracle_mech):
 
 @pytest.mark.parametrize("name,n,te", [("M13", 300, 1e-4), ("M53", 67, 2e-6), ("M111", 24, 2e-7)])
 def test_ros4_group_parity(ck, gmech, oracle_mech, name, n, te):
-    """Workgroup kernel: one wavefront per reactor for N <= 64, two for N = 112 (Gauss-Jordan inverse)."""
+    """Workgroup kernel: one wavefront per reactor for N <= 64, four for N = 112 (rows over thread pairs)."""
     g, om = gmech(name), oracle_mech(name)
     y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=1009)
     res, orc = _integrate_both(ck, g, om, y, P, te, "ros4", "group")
@@ -199,6 +199,46 @@ def test_resume_and_batch_independence(ck, gmech, kernel):
     idx = [5, 64, 95]
     alone = ck.integrate(g, dev(y[:, idx]), dev(P[idx]), te, kernel=kernel)
     assert torch.equal(alone["y"], full["y"][:, idx])
+
+
+@pytest.mark.parametrize("name,kernel", [("M53", "wave"), ("M111", "group")])
+def test_concurrent_streams_without_workspace(ck, gmech, name, kernel):
+    """Two batches integrated at once on two streams, both with the library-owned workspace, give
+    what each gives alone: the persistent kernels' queue counters and parking areas are per stream.
+    One workgroup per CU each, so the two grids are resident together; t is not passed, so a reactor
+    taken twice from a shared queue would be integrated twice (on M111 that moves each reactor's
+    weighted error by 4 to 16).  The single-wavefront kernels are compared bit for bit; the
+    four-wavefront GROUP form adds reaction contributions from its wavefronts with LDS atomics in a
+    timing-dependent order, so it is compared to rounding: over the 1200-9800 stiff steps of this
+    workload rounding alone moves the weighted error to ~1e-6 (the oracle against itself with y0
+    perturbed by one ulp reaches 4.5e-7 on 70 of these reactors), so the bar is 1e-5, five decades
+    under what a shared queue or parking area produces."""
+    g = gmech(name)
+    ya, Pa = synth.reactor_states(g.n_species, 700, RECIPE[name], seed=1010)
+    yb, Pb = synth.reactor_states(g.n_species, 450, RECIPE[name], seed=1011)
+    te = 2e-8
+    alone_a = ck.integrate(g, dev(ya), dev(Pa), te, kernel=kernel, blocks_per_cu=1)
+    alone_b = ck.integrate(g, dev(yb), dev(Pb), te, kernel=kernel, blocks_per_cu=1)
+    da, pa, db, pb = dev(ya), dev(Pa), dev(yb), dev(Pb)
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    for _ in range(2):
+        with torch.cuda.stream(sa):
+            ra = ck.integrate(g, da, pa, te, kernel=kernel, blocks_per_cu=1, stream=sa)
+        with torch.cuda.stream(sb):
+            rb = ck.integrate(g, db, pb, te, kernel=kernel, blocks_per_cu=1, stream=sb)
+        torch.cuda.synchronize()
+        for r, alone in ((ra, alone_a), (rb, alone_b)):
+            assert torch.equal(r["status"], alone["status"])
+            if g.N <= 64:
+                assert torch.equal(r["n_accept"], alone["n_accept"])
+                assert torch.equal(r["y"], alone["y"])
+            else:
+                yr, ya_ = r["y"].cpu().numpy(), alone["y"].cpu().numpy()
+                eT, _ = state_rel_error(yr, ya_)
+                ew = weighted_error(yr, ya_)
+                print(f"[streams {name} {kernel}] weighted {ew:.2e} rel T {eT:.2e}", flush=True)
+                assert eT <= 1e-6 and ew <= 1e-5
 
 
 @pytest.mark.parametrize("name,n,te", [("M13", 512, 1e-4), ("M53", 67, 2e-6)])
