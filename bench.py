@@ -119,9 +119,10 @@ def parse():
     ap.add_argument("--rhs-batches", type=int, default=8, help="distinct state batches cycled in the RHS leg")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 8 per host core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--suite", default="integrate", choices=["integrate", "batching", "precision", "serving"],
+    ap.add_argument("--suite", default="integrate", choices=["integrate", "batching", "precision", "serving", "methods"],
                     help="integrate: the headline line; batching / precision / serving: the three production "
-                         "forms (one JSON line each, bounded workloads)")
+                         "forms; methods: small configuration with both integrators, transfers, analytic vs "
+                         "forward-difference Jacobian (one JSON line each, bounded workloads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (counter calibration) and exit")
     return ap.parse_args()
@@ -278,6 +279,107 @@ def suite_serving(a):
                       "t_end log-uniform 1e-8-1e-6 s, 200 GB budget"}
 
 
+def _median_time(ck, torch, g, y, P, t_end, warmup=3, runs=5, **opts):
+    """Median over `runs` timed integrations (HIP events) after `warmup` untimed ones."""
+    for _ in range(warmup):
+        _timed_integrate(ck, torch, g, y, P, t_end, **opts)
+    times, r = [], None
+    for _ in range(runs):
+        r, dt = _timed_integrate(ck, torch, g, y, P, t_end, **opts)
+        times.append(dt)
+    return r, float(np.median(times))
+
+
+def _oracle_rate(path, y, P, t_end, n, threads, **kw):
+    from oracle import oracle as O
+    m = O.Mechanism(path)
+    ys, Ps = np.ascontiguousarray(y[:, :n]), np.ascontiguousarray(P[:n])
+    t0 = time.perf_counter()
+    res = m.integrate(ys, Ps, t_end, "ros4", nthreads=threads, **kw)
+    dt = time.perf_counter() - t0
+    return {"reactors": n, "threads": threads, "seconds": dt, "reactors_per_s": n / dt,
+            "mean_steps": float(np.mean(res["n_accept"] + res["n_reject"]))}
+
+
+def suite_methods(a):
+    """The small configuration (13 species x 1024 reactors to 1e-4 s) with ROS4 and RKF45, a stiffness
+    census of its initial states, the oracle on all host cores and on one; the rate with host-to-device
+    and device-to-host transfers included; and ROS4 with the analytic Jacobian against forward
+    differences (53 species), with the oracle's one-core rate on the 53-species workload."""
+    import torch
+
+    from paper_1608_05794_amd import ck, synth
+    cores = len(os.sched_getaffinity(0))
+    out = {"suite": "methods", "data": "synthetic", "dtype": "f64", "host_cores": cores}
+    stat = lambda r: torch.bincount(r["status"].to(torch.int64), minlength=4).tolist()
+    steps = lambda r: (r["n_accept"] + r["n_reject"]).to(torch.float64)
+
+    # small configuration: ROS4 and RKF45 (RKF45 capped: its steps follow the stiffness, see census)
+    path = synth.mechanism_file("M13")
+    g = ck.Mechanism(path)
+    n, te = 1024, 1e-4
+    y0, P0 = synth.reactor_states(13, n, "small", seed=1001)
+    y, P = torch.as_tensor(y0, device="cuda"), torch.as_tensor(P0, device="cuda")
+    small = {"workload": f"M13 x {n} reactors to {te:g} s, rtol 1e-8, atol 1e-12"}
+    for method, cap in (("ros4", 1_000_000), ("rkf45", 100_000)):
+        r, dt = _median_time(ck, torch, g, y, P, te, method=method, kernel="wave", max_steps=cap)
+        s = steps(r)
+        small[method] = {"seconds_median_of_5": dt, "reactors_per_s": n / dt,
+                         "reactor_steps_per_s": float(s.sum().item()) / dt, "mean_steps": float(s.mean().item()),
+                         "max_steps_cap": cap, "status_histogram": stat(r)}
+        print(f"methods small {method}: {dt * 1e3:.2f} ms, status {stat(r)}", file=sys.stderr, flush=True)
+    # stiffness census: spectral radius of J at the initial states; explicit RKF45 needs about
+    # t_end * rho / 3 steps (stability-bound)
+    J = ck.jac(g, y, P).cpu().numpy().T.reshape(n, 14, 14)
+    rho = np.abs(np.linalg.eigvals(J)).max(axis=1)
+    small["stiffness_census"] = {"rho_percentiles_10_50_90": [float(v) for v in np.percentile(rho, [10, 50, 90])],
+                                 "rkf45_steps_estimate_median": float(np.median(rho) * te / 3)}
+    small["oracle_all_cores"] = _oracle_rate(path, y0, P0, te, n, cores)
+    small["oracle_one_core"] = _oracle_rate(path, y0, P0, te, 128, 1)
+    # transfers included: pinned host state in, integrate, state / status / counters out
+    hy = torch.empty(y0.shape, dtype=torch.float64, pin_memory=True)
+    hy.copy_(torch.as_tensor(y0))
+    hP = torch.empty(P0.shape, dtype=torch.float64, pin_memory=True)
+    hP.copy_(torch.as_tensor(P0))
+    oy = torch.empty(y0.shape, dtype=torch.float64, pin_memory=True)
+    ost = torch.empty(n, dtype=torch.int32, pin_memory=True)
+    times = []
+    for i in range(8):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dy, dP = hy.to("cuda", non_blocking=True), hP.to("cuda", non_blocking=True)
+        r = ck.integrate(g, dy, dP, te, method="ros4", kernel="wave", inplace=True)
+        oy.copy_(r["y"], non_blocking=True)
+        ost.copy_(r["status"], non_blocking=True)
+        torch.cuda.synchronize()
+        if i >= 3:
+            times.append(time.perf_counter() - t0)
+    small["ros4_with_transfers"] = {"seconds_median_of_5": float(np.median(times)),
+                                    "reactors_per_s": n / float(np.median(times))}
+    out["small"] = small
+
+    # analytic Jacobian against forward differences (the paper's own set-up), 53 species
+    path = synth.mechanism_file("M53")
+    g = ck.Mechanism(path)
+    n, te = 8192, 1e-7
+    y0, P0 = synth.reactor_states(53, n, "mid", seed=1002)
+    y, P = torch.as_tensor(y0, device="cuda"), torch.as_tensor(P0, device="cuda")
+    jac = {"workload": f"M53 x {n} reactors, ROS4 to {te:g} s, rtol 1e-8, atol 1e-12"}
+    for kind in ("analytic", "fd"):
+        r, dt = _median_time(ck, torch, g, y, P, te, warmup=1, runs=3, kernel="wave", jacobian=kind)
+        s = steps(r)
+        jac[kind] = {"seconds_median_of_3": dt, "reactors_per_s": n / dt,
+                     "reactor_steps_per_s": float(s.sum().item()) / dt, "mean_steps": float(s.mean().item()),
+                     "status_histogram": stat(r)}
+        print(f"methods jacobian {kind}: {dt:.2f} s", file=sys.stderr, flush=True)
+    jac["analytic_speedup"] = jac["fd"]["seconds_median_of_3"] / jac["analytic"]["seconds_median_of_3"]
+    out["jacobian"] = jac
+    # the oracle on one core for the headline workload's states (ROS4 to 1e-3 s)
+    y0, P0 = synth.reactor_states(53, 4, "mid", seed=1002)
+    out["oracle_one_core_M53_1e-3"] = _oracle_rate(path, y0, P0, 1e-3, 4, 1)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -287,7 +389,8 @@ def main():
     import torch
 
     if a.suite != "integrate":
-        fn = {"batching": suite_batching, "precision": suite_precision, "serving": suite_serving}[a.suite]
+        fn = {"batching": suite_batching, "precision": suite_precision, "serving": suite_serving,
+              "methods": suite_methods}[a.suite]
         print(json.dumps(fn(a)), flush=True)
         return
 
