@@ -191,8 +191,12 @@ __device__ __forceinline__ void species_pass(const DevMech &M, double y, double 
 }
 
 // Rates of progress into WD (FIRST window only) and d wdot/dC for columns [c0, c0 + win) into JC.
+// The column scatter of a reaction needs c k_f, c k_r and R_net dc/d[M] besides the concentrations:
+// mode 1 stores them in this thread's column of `cache` (entry (3 it + v) * T for the thread's it-th
+// reaction), mode 2 reads them back instead of evaluating the rate constants again.
 template <int W, bool JAC>
-__device__ __forceinline__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, double Ctot, int c0, int win, bool first) {
+__device__ __forceinline__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, double Ctot, int c0, int win,
+                                              bool first, double *cache = nullptr, int mode = 0) {
     using G = Grp<W>;
     const int nr = M.nrxn, ns = M.nsp, tid = G::tid();
     if (JAC) {
@@ -203,20 +207,47 @@ __device__ __forceinline__ void reaction_pass(const DevMech &M, const Lds &L, co
     auto Cg = [&](int k) { return L.C[k]; };
     auto Gg = [&](int k) { return L.G[k]; };
     auto Hg = [&](int k) { return L.H[k]; };
-    for (int i = tid; i < nr; i += G::T) {
+    int it = 0;
+    for (int i = tid; i < nr; i += G::T, it++) {
         const RxnRec R = M.rx[i];
         const int nmax = __builtin_amdgcn_readfirstlane(R.blk_slots);
         Slots S;
         load_slots(R, Cg, S, nmax);
-        Rate q;
-        reaction_rate<JAC>(M, R, S, nmax, t, Ctot, Cg, Gg, Hg, q);
-        const double Rn = q.kf * q.pf - q.kr * q.pr;
-        if (first) {
-            const double qi = q.c * Rn;
+        double ckf, ckr, rdm;
+        if (JAC && mode == 2) {
+            ckf = cache[(3 * it) * G::T];
+            ckr = cache[(3 * it + 1) * G::T];
+            rdm = cache[(3 * it + 2) * G::T];
+        } else {
+            Rate q;
+            reaction_rate<JAC>(M, R, S, nmax, t, Ctot, Cg, Gg, Hg, q);
+            const double Rn = q.kf * q.pf - q.kr * q.pr;
+            if (first) {
+                const double qi = q.c * Rn;
 #pragma unroll
-            for (int s = 0; s < kMaxSlots; s++) {
-                if (s >= nmax) break;
-                if (S.sgn[s] != 0) atomicAdd(&L.WD[S.sp[s]], (S.sgn[s] * S.nu[s]) * qi);
+                for (int s = 0; s < kMaxSlots; s++) {
+                    if (s >= nmax) break;
+                    if (S.sgn[s] != 0) atomicAdd(&L.WD[S.sp[s]], (S.sgn[s] * S.nu[s]) * qi);
+                }
+            }
+            ckf = q.c * q.kf;
+            ckr = q.c * q.kr;
+            rdm = JAC ? Rn * q.dcdM : 0.0;
+            if (JAC && first) {
+                const double dqT = q.c * (q.kf * q.dlnkf * q.pf - q.kr * q.dlnkr * q.pr) + Rn * q.dcdT;
+#pragma unroll
+                for (int a = 0; a < kMaxSlots; a++) {
+                    if (a >= nmax) break;
+                    if (S.sgn[a] == 0) continue;
+                    const double v = S.sgn[a] * S.nu[a];
+                    atomicAdd(&L.DWT[S.sp[a]], v * dqT);
+                    if (q.dcdM != 0.0) atomicAdd(&L.TB[S.sp[a]], v * rdm);
+                }
+            }
+            if (JAC && mode == 1) {
+                cache[(3 * it) * G::T] = ckf;
+                cache[(3 * it + 1) * G::T] = ckr;
+                cache[(3 * it + 2) * G::T] = rdm;
             }
         }
         if (JAC) {
@@ -226,24 +257,20 @@ __device__ __forceinline__ void reaction_pass(const DevMech &M, const Lds &L, co
                 const int col = S.sp[b] - c0;
                 if (S.sgn[b] == 0 || col < 0 || col >= win) continue;
                 const double d = dprod_slot(S, b, nmax);
-                const double dq = q.c * (S.sgn[b] < 0 ? q.kf * d : -q.kr * d);
+                const double dq = S.sgn[b] < 0 ? ckf * d : -ckr * d;
 #pragma unroll
                 for (int a = 0; a < kMaxSlots; a++) {
                     if (a >= nmax) break;
                     if (S.sgn[a] != 0) atomicAdd(&L.JC[S.sp[a] * L.ldj + col], (S.sgn[a] * S.nu[a]) * dq);
                 }
             }
-            const int eb = R.eff_begin, ec = rx_neff(R.meta);
-            const double dqT = q.c * (q.kf * q.dlnkf * q.pf - q.kr * q.dlnkr * q.pr) + Rn * q.dcdT;
+            if (rdm != 0.0) {
+                const int eb = R.eff_begin, ec = rx_neff(R.meta);
 #pragma unroll
-            for (int a = 0; a < kMaxSlots; a++) {
-                if (a >= nmax) break;
-                if (S.sgn[a] == 0) continue;
-                const double v = S.sgn[a] * S.nu[a];
-                if (first) atomicAdd(&L.DWT[S.sp[a]], v * dqT);
-                if (q.dcdM != 0.0) {
-                    const double base = v * Rn * q.dcdM;
-                    if (first) atomicAdd(&L.TB[S.sp[a]], base);
+                for (int a = 0; a < kMaxSlots; a++) {
+                    if (a >= nmax) break;
+                    if (S.sgn[a] == 0) continue;
+                    const double base = (S.sgn[a] * S.nu[a]) * rdm;
                     for (int e = 0; e < ec; e++) {
                         const EffRec E = M.eff[eb + e];
                         const int col = E.sp - c0;
@@ -479,10 +506,14 @@ __device__ __forceinline__ void iteration_rows_half(const DevMech &M, const Lds 
     double colH = 0.0, jcp = 0.0;                   // jcp: this half's part of sum_l JC[kr][l] C_l
 #pragma unroll
     for (int j = 0; j < H; j++) a[j] = 0.0;
+    // the first window's per-reaction scatter scalars, kept for the second in this workgroup's park
+    // slice (free until the inverse is parked)
+    const bool keep = L.rows != nullptr && 3 * ((M.nrxn + G::T - 1) / G::T) <= H;
+    double *cache = keep ? L.rows + opaque(tid) : nullptr;
 #pragma unroll
     for (int w = 0; w < 2; w++) {
         const int c0 = w * H - 1;                   // window w: matrix columns [w H, w H + H)
-        reaction_pass<W, true>(M, L, x.t, x.Ctot, c0, H, w == 0);
+        reaction_pass<W, true>(M, L, x.t, x.Ctot, c0, H, w == 0, cache, keep ? (w == 0 ? 1 : 2) : 0);
         if (w == 0) f = finish_rhs<W>(M, L, x);
         if (rvalid && half == w) {
             const double *r = &L.JC[kr * L.ldj];

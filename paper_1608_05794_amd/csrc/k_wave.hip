@@ -166,27 +166,58 @@ __device__ __forceinline__ void species_pass(const DevMech &M, const double (&y)
 // d wdot / dT at fixed C (into DWT).  With a column window [c0, c0 + win) only
 // those columns of d wdot / dC are accumulated, and WD, TB and DWT only when
 // `first` is set.
+// Column scatter of reaction i needs three scalars besides the concentrations: c k_f, c k_r and
+// R_net dc/d[M].  mode 1 stores them in this lane's column of `cache` (entry (3 it + v) * 64 for
+// the lane's it-th reaction); mode 2 reads them back instead of evaluating the rate constants, so
+// a later column window costs a record load and the scatter only.
 template <bool JAC>
 __device__ __forceinline__ void reaction_pass(const DevMech &M, const Lds &L, const TPow &t, double Ctot, int c0, int win,
-                              bool first) {
+                              bool first, double *cache = nullptr, int mode = 0) {
     const int nr = M.nrxn;
     auto Cg = [&](int k) { return L.C[k]; };
     auto Gg = [&](int k) { return L.G[k]; };
     auto Hg = [&](int k) { return L.H[k]; };
-    for (int i = lane_fresh(); i < nr; i += 64) {
+    int it = 0;
+    for (int i = lane_fresh(); i < nr; i += 64, it++) {
         const RxnRec R = M.rx[i];
         const int nmax = __builtin_amdgcn_readfirstlane(R.blk_slots);
         Slots S;
         load_slots(R, Cg, S, nmax);
-        Rate q;
-        reaction_rate<JAC>(M, R, S, nmax, t, Ctot, Cg, Gg, Hg, q);
-        const double Rn = q.kf * q.pf - q.kr * q.pr;
-        if (first) {
-            const double qi = q.c * Rn;
+        double ckf, ckr, rdm;
+        if (JAC && mode == 2) {
+            ckf = cache[(3 * it) * 64];
+            ckr = cache[(3 * it + 1) * 64];
+            rdm = cache[(3 * it + 2) * 64];
+        } else {
+            Rate q;
+            reaction_rate<JAC>(M, R, S, nmax, t, Ctot, Cg, Gg, Hg, q);
+            const double Rn = q.kf * q.pf - q.kr * q.pr;
+            if (first) {
+                const double qi = q.c * Rn;
 #pragma unroll
-            for (int s = 0; s < kMaxSlots; s++) {
-                if (s >= nmax) break;
-                if (S.sgn[s] != 0) atomicAdd(&L.WD[S.sp[s]], (S.sgn[s] * S.nu[s]) * qi);
+                for (int s = 0; s < kMaxSlots; s++) {
+                    if (s >= nmax) break;
+                    if (S.sgn[s] != 0) atomicAdd(&L.WD[S.sp[s]], (S.sgn[s] * S.nu[s]) * qi);
+                }
+            }
+            ckf = q.c * q.kf;
+            ckr = q.c * q.kr;
+            rdm = JAC ? Rn * q.dcdM : 0.0;
+            if (JAC && first) {
+                const double dqT = q.c * (q.kf * q.dlnkf * q.pf - q.kr * q.dlnkr * q.pr) + Rn * q.dcdT;
+#pragma unroll
+                for (int a = 0; a < kMaxSlots; a++) {
+                    if (a >= nmax) break;
+                    if (S.sgn[a] == 0) continue;
+                    const double v = S.sgn[a] * S.nu[a];
+                    atomicAdd(&L.DWT[S.sp[a]], v * dqT);
+                    if (q.dcdM != 0.0) atomicAdd(&L.TB[S.sp[a]], v * rdm);
+                }
+            }
+            if (JAC && mode == 1) {
+                cache[(3 * it) * 64] = ckf;
+                cache[(3 * it + 1) * 64] = ckr;
+                cache[(3 * it + 2) * 64] = rdm;
             }
         }
         if (JAC) {
@@ -196,24 +227,20 @@ __device__ __forceinline__ void reaction_pass(const DevMech &M, const Lds &L, co
                 const int col = S.sp[b] - c0;
                 if (S.sgn[b] == 0 || col < 0 || col >= win) continue;
                 const double d = dprod_slot(S, b, nmax);
-                const double dq = q.c * (S.sgn[b] < 0 ? q.kf * d : -q.kr * d);
+                const double dq = S.sgn[b] < 0 ? ckf * d : -ckr * d;
 #pragma unroll
                 for (int a = 0; a < kMaxSlots; a++) {
                     if (a >= nmax) break;
                     if (S.sgn[a] != 0) atomicAdd(&L.JC[S.sp[a] * L.ldj + col], (S.sgn[a] * S.nu[a]) * dq);
                 }
             }
-            const int eb = R.eff_begin, ec = rx_neff(R.meta);
-            const double dqT = q.c * (q.kf * q.dlnkf * q.pf - q.kr * q.dlnkr * q.pr) + Rn * q.dcdT;
+            if (rdm != 0.0) {
+                const int eb = R.eff_begin, ec = rx_neff(R.meta);
 #pragma unroll
-            for (int a = 0; a < kMaxSlots; a++) {
-                if (a >= nmax) break;
-                if (S.sgn[a] == 0) continue;
-                const double v = S.sgn[a] * S.nu[a];
-                if (first) atomicAdd(&L.DWT[S.sp[a]], v * dqT);
-                if (q.dcdM != 0.0) {
-                    const double base = v * Rn * q.dcdM;
-                    if (first) atomicAdd(&L.TB[S.sp[a]], base);
+                for (int a = 0; a < kMaxSlots; a++) {
+                    if (a >= nmax) break;
+                    if (S.sgn[a] == 0) continue;
+                    const double base = (S.sgn[a] * S.nu[a]) * rdm;
                     for (int e = 0; e < ec; e++) {
                         const EffRec E = M.eff[eb + e];
                         const int col = E.sp - c0;
@@ -384,8 +411,9 @@ __device__ __forceinline__ void jac_rows(const DevMech &M, const Lds &L, double 
 
 // f(y) and this lane's row of M = dg I - J (FP64 registers) for N <= NP <= 64, with d wdot/dC
 // staged in NWIN column windows of WIN columns (NWIN * WIN >= ns).  The reaction pass runs once
-// per window (rates are recomputed), which keeps JC at ns * (WIN | 1) doubles of LDS; raw window
-// entries wait in the row registers until the chain-rule scalars of the row are known.
+// per window, which keeps JC at ns * (WIN | 1) doubles of LDS; the second window reuses the first
+// window's rate constants when they fit the park slice (else it recomputes them).  Raw window
+// entries wait in the park slice until the chain-rule scalars of the row are known.
 template <int NP, int NWIN, int WIN>
 __device__ __forceinline__ void jac_rows_win(const DevMech &M, const Lds &L, double y, double P, double dg, double (&a)[NP],
                              double &f) {
@@ -398,12 +426,17 @@ __device__ __forceinline__ void jac_rows_win(const DevMech &M, const Lds &L, dou
     const int k = lane - 1;
     const bool valid = lane >= 1 && lane <= ns;
     double jcc = 0.0, colH = 0.0, colJ = 0.0;
+    // per-reaction scatter scalars of the first window, kept for the second in the park rows that
+    // the second window's raw entries fill only after its reaction pass
+    static_assert(NWIN <= 2, "the scalar cache serves one later window");
+    const bool keep = NWIN == 2 && 1 + WIN + 3 * ((M.nrxn + 63) / 64) <= NP;
+    double *cache = L.park + (1 + WIN) * 64 + lane_fresh();
     for (int w = 0; w < NWIN; w++) {
         const int c0 = opaque(w * WIN);
         const int tot = ns * L.ldj;
         for (int e = lane; e < tot; e += 64) L.JC[e] = 0.0;
         __syncthreads();
-        reaction_pass<true>(M, L, x.t, x.Ctot, c0, WIN, w == 0);
+        reaction_pass<true>(M, L, x.t, x.Ctot, c0, WIN, w == 0, cache, keep ? (w == 0 ? 1 : 2) : 0);
         if (w == 0) finish_rhs<1>(M, L, x, ff);
         // raw d wdot_k / dC_(c0+j), parked in the workspace (column 1 + c0 + j of the row) until the
         // chain-rule scalars of the row are known, so no row registers are live across a reaction pass
