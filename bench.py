@@ -34,11 +34,11 @@ PEAK_FP64_VECTOR = 78.6e12         # FLOP/s, MI355X FP64 vector (VALU)
 TRAFFIC_REF = {
     "sources": ["paper_1608_05794_amd/csrc/k_wave.hip", "paper_1608_05794_amd/csrc/kinetics.h",
                 "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h"],
-    "sha256": "1c11169cc564b2e6627acb35b633d5c332b8e3f174332e2b6f3b101ccd75fed2",
+    "sha256": "23406a764c030a3fa7dabb51cb1ccdb1739b0d9706d5395e3b5a47dc368e48a1",
     "args": {"mech": "M53", "reactors": 131072, "t_end": 1e-3, "kernel": "wave", "precision": "fp64",
              "launch_steps": 2000},
-    "fetch_kib_per_launch": 3765407590.3, "fetch_factor": 1048576.0 / 524303.75,
-    "write_kib_per_launch": 5488711913.25, "write_factor": 1.0,
+    "fetch_kib_per_launch": 4031331986.76, "fetch_factor": 1048576.0 / 524302.5,
+    "write_kib_per_launch": 6247536145.86, "write_factor": 1.0,
 }
 TRANSCENDENTAL_FLOPS = 20           # FP64 operations charged per exp / log / log10 / exp10
 
