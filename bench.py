@@ -33,7 +33,8 @@ PEAK_FP64_VECTOR = 78.6e12         # FLOP/s, MI355X FP64 vector (VALU)
 # matches; otherwise the traffic is reported as null.
 TRAFFIC_REF = {
     "sources": ["paper_1608_05794_amd/csrc/k_wave.hip", "paper_1608_05794_amd/csrc/kinetics.h",
-                "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h"],
+                "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h",
+                "paper_1608_05794_amd/csrc/mech.hip"],
     "sha256": "23406a764c030a3fa7dabb51cb1ccdb1739b0d9706d5395e3b5a47dc368e48a1",
     "args": {"mech": "M53", "reactors": 131072, "t_end": 1e-3, "kernel": "wave", "precision": "fp64",
              "launch_steps": 2000},

@@ -178,10 +178,13 @@ extern "C" int ck_mechanism_load(const char *path, int device, ck_mech **out) {
             for (int j = 0; j < 21; j++) spd[size_t(3 + 21 * rg + j) * ns + k] = c[j];
         }
     }
-    // reactions sorted by type (stable), so wavefront lanes mostly share a branch
+    // Reactions sorted by type (stable), the most complex first: the kernels hand consecutive
+    // blocks of 64 reactions to the lanes of a wavefront, and a block pays for the most complex
+    // type it holds, so the few third-body and fall-off reactions share the leading blocks and
+    // the ragged last block holds elementary reactions only.
     std::vector<int> order(nr);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hm.rx[a].type < hm.rx[b].type; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hm.rx[a].type > hm.rx[b].type; });
     std::vector<RxnRec> rx(std::max(nr, 1));
     std::vector<FallRec> fall;
     std::vector<EffRec> eff;
