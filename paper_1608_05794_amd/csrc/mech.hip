@@ -178,13 +178,18 @@ extern "C" int ck_mechanism_load(const char *path, int device, ck_mech **out) {
             for (int j = 0; j < 21; j++) spd[size_t(3 + 21 * rg + j) * ns + k] = c[j];
         }
     }
-    // Reactions sorted by type (stable), the most complex first: the kernels hand consecutive
-    // blocks of 64 reactions to the lanes of a wavefront, and a block pays for the most complex
-    // type it holds, so the few third-body and fall-off reactions share the leading blocks and
-    // the ragged last block holds elementary reactions only.
+    // Reactions sorted by type (stable), the most complex first, and within a type by species slot
+    // count, the fewest first: the kernels hand consecutive blocks of 64 reactions to the lanes of
+    // a wavefront, and a block pays for the most complex type it holds and loops over its largest
+    // slot count.  So the few third-body and fall-off reactions share the leading blocks, topped up
+    // with the smallest elementary reactions, and the ragged last block holds elementary ones only.
     std::vector<int> order(nr);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hm.rx[a].type > hm.rx[b].type; });
+    auto slots = [&](int i) { return hm.rx[i].rsp.size() + hm.rx[i].psp.size(); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (hm.rx[a].type != hm.rx[b].type) return hm.rx[a].type > hm.rx[b].type;
+        return slots(a) < slots(b);
+    });
     std::vector<RxnRec> rx(std::max(nr, 1));
     std::vector<FallRec> fall;
     std::vector<EffRec> eff;
