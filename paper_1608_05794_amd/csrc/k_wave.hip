@@ -554,9 +554,10 @@ __device__ __forceinline__ double lu_solve(const double (&a)[NP], const LU<NP> &
 // ---------------------------------------------------------------------------------------
 // one steps
 // ---------------------------------------------------------------------------------------
-// Window count and width of the staged d wdot/dC for a padded size NP, and whether the LU
-// rows are parked in the workspace while the stage right-hand sides are evaluated (so the
-// source-term code does not share the register file with them).
+// Window count and width of the staged d wdot/dC for a padded size NP, and whether the kernel
+// uses a parking slice in the workspace (raw Jacobian window entries and the first window's
+// per-reaction rate scalars; the forward-difference step also parks its Jacobian columns and
+// its LU rows there).
 template <int NP>
 struct WaveShape {
     static constexpr int NWIN = NP > 32 ? 2 : 1;
@@ -596,14 +597,12 @@ struct Ros4Wave {
         lu_factor<NP>(a, lu);
         const double ih = 1.0 / h;
         const double u1 = lu_solve<NP>(a, lu, f);
-        if (SH::PARK) park_rows<NP>(L, a);
+        // the factored rows stay in registers across the stage source terms (it fits without spills)
         double yt[1] = {y + Ros4::a21 * u1}, ft[1];
         rhs_wave<1>(M, L, yt, P, ft);
-        if (SH::PARK) unpark_rows<NP>(L, a);
         const double u2 = lu_solve<NP>(a, lu, ft[0] + (Ros4::c21 * u1) * ih);
         yt[0] = y + Ros4::a31 * u1 + Ros4::a32 * u2;
         rhs_wave<1>(M, L, yt, P, ft);
-        if (SH::PARK) unpark_rows<NP>(L, a);
         const double u3 = lu_solve<NP>(a, lu, ft[0] + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
         const double u4 = lu_solve<NP>(a, lu, ft[0] + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
         ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
