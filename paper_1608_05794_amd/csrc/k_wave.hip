@@ -426,27 +426,28 @@ __device__ __forceinline__ void jac_rows_win(const DevMech &M, const Lds &L, dou
     const int k = lane - 1;
     const bool valid = lane >= 1 && lane <= ns;
     double jcc = 0.0, colH = 0.0, colJ = 0.0;
-    // per-reaction scatter scalars of the first window, kept for the second in the park rows that
-    // the second window's raw entries fill only after its reaction pass
+    // per-reaction scatter scalars of the first window, kept in the park slice for the second
     static_assert(NWIN <= 2, "the scalar cache serves one later window");
-    const bool keep = NWIN == 2 && 1 + WIN + 3 * ((M.nrxn + 63) / 64) <= NP;
-    double *cache = L.park + (1 + WIN) * 64 + lane_fresh();
+    const bool keep = NWIN == 2 && 3 * ((M.nrxn + 63) / 64) <= NP;
+    double *cache = L.park + lane_fresh();
+#pragma unroll
     for (int w = 0; w < NWIN; w++) {
-        const int c0 = opaque(w * WIN);
+        const int c0 = w * WIN;
         const int tot = ns * L.ldj;
         for (int e = lane; e < tot; e += 64) L.JC[e] = 0.0;
         __syncthreads();
         reaction_pass<true>(M, L, x.t, x.Ctot, c0, WIN, w == 0, cache, keep ? (w == 0 ? 1 : 2) : 0);
         if (w == 0) finish_rhs<1>(M, L, x, ff);
-        // raw d wdot_k / dC_(c0+j), parked in the workspace (column 1 + c0 + j of the row) until the
-        // chain-rule scalars of the row are known, so no row registers are live across a reaction pass
+        // raw d wdot_k / dC_(c0+j) into column 1 + c0 + j of the row registers; the chain-rule
+        // scalars of the row are applied once every window is in
         const double *row = &L.JC[(valid ? k : 0) * L.ldj];
-        double *pk = L.park + lane;
-        for (int j = 0; j < WIN && 1 + c0 + j < NP; j++) {
+#pragma unroll
+        for (int j = 0; j < WIN; j++) {
+            if (1 + c0 + j >= NP) break;
             const bool in = c0 + j < ns;
             const double v = (valid && in) ? row[j] : 0.0;
             if (in) jcc += v * L.C[c0 + j];
-            pk[(1 + c0 + j) * 64] = v;
+            a[1 + c0 + j] = v;
         }
         if (valid && k >= c0 && k < c0 + WIN)
             for (int r = 0; r < ns; r++) {
@@ -455,11 +456,6 @@ __device__ __forceinline__ void jac_rows_win(const DevMech &M, const Lds &L, dou
                 colJ += v;
             }
         __syncthreads();
-    }
-    {
-        const double *pk = L.park + lane;
-#pragma unroll
-        for (int j = 1; j < NP; j++) a[j] = pk[j * 64];
     }
     f = ff[0];
     const Chain c = chain_rule(M, L, x, valid, k, y, bcast(f, 0), jcc, colH, colJ);
