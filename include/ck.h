@@ -150,10 +150,12 @@ int ck_jacobian_eval(const ck_mech *m, int64_t n, const double *y, int64_t ld, c
  * the mechanism is called on, kept (and grown when a call needs more, which
  * waits for the device) until ck_mechanism_free.
  * Lane kernel: per-reactor scratch, linear in n.  Wavefront kernel: a
- * 256-byte queue counter.  Workgroup kernel with N > 64: the counter plus
- * the parked Gauss-Jordan inverses of the resident workgroups (2 per compute
- * unit of the mechanism's device, 128 N' doubles each with N' = N rounded up
- * to a multiple of 8), independent of n.  Returns 0 on a device query error.
+ * 256-byte queue counter, plus for 32 < N' <= 64 (N' = N rounded up to a
+ * multiple of 8) a parking slice of 64 N' doubles per resident wavefront (8
+ * per compute unit of the mechanism's device).  Workgroup kernel with N > 64:
+ * the counter plus a parking slice of 128 N' doubles per resident workgroup
+ * (2 per compute unit).  Independent of n except for the lane kernel.
+ * Returns 0 on a device query error.
  */
 size_t ck_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts *o);
 

@@ -13,8 +13,9 @@
 //   - N > 64: four wavefronts, each row split over a pair of adjacent threads
 //     (half rows of N'/2 doubles), d wdot/dC staged in LDS in two column
 //     windows (one per half), so two reactors fit in one CU's LDS and two
-//     wavefronts fit each SIMD.  The inverse is parked in a per-workgroup
-//     slice of the workspace while the stage right-hand sides are evaluated.
+//     wavefronts fit each SIMD.  The inverse stays in registers across the
+//     stage right-hand sides; a per-workgroup slice of the workspace carries
+//     the first Jacobian window's per-reaction rate scalars to the second.
 // Reactors come from the same device work queue as the wavefront kernels.
 #include "ck_internal.h"
 #include "kinetics.h"
@@ -42,7 +43,7 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
 //   JC[ns * ldj + 128] TB[ns] DWT[ns] TROW[ns + 128]
 struct Lds {
     double *C, *G, *H, *WD, *IW, *VX, *RED, *PB, *BS, *XS, *JC, *TB, *DWT, *TROW;
-    double *rows;   // parked inverse of this workgroup ([NP][64 W], global memory), or null
+    double *rows;   // this workgroup's park slice (global memory), or null
     // half-row kernel only: per-row chain-rule scalars and pivot orders, [128] each
     double *RA, *RB, *RC, *RJ;
     int *ORD;
@@ -507,7 +508,7 @@ __device__ __forceinline__ void iteration_rows_half(const DevMech &M, const Lds 
 #pragma unroll
     for (int j = 0; j < H; j++) a[j] = 0.0;
     // the first window's per-reaction scatter scalars, kept for the second in this workgroup's park
-    // slice (free until the inverse is parked)
+    // slice
     const bool keep = L.rows != nullptr && 3 * ((M.nrxn + G::T - 1) / G::T) <= H;
     double *cache = keep ? L.rows + opaque(tid) : nullptr;
 #pragma unroll
@@ -653,17 +654,7 @@ struct Ros4CoopHalf {
     static constexpr double qinv = 0.25;
     static constexpr int H = NP / 2;
     static constexpr bool kHalf = true;
-    static constexpr size_t kRows = size_t(H) * 256;   // parked doubles per workgroup
-    __device__ static __forceinline__ void park(const Lds &L, const double (&a)[H]) {
-        double *r = L.rows + opaque(Grp<4>::tid());
-#pragma unroll
-        for (int j = 0; j < H; j++) r[j * 256] = a[j];
-    }
-    __device__ static __forceinline__ void unpark(const Lds &L, double (&a)[H]) {
-        const double *r = L.rows + opaque(Grp<4>::tid());
-#pragma unroll
-        for (int j = 0; j < H; j++) a[j] = r[j * 256];
-    }
+    static constexpr size_t kRows = size_t(H) * 256;   // park-slice doubles per workgroup
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h,
                                                 double &ynew, double &e) {
         double a[H];
@@ -674,12 +665,9 @@ struct Ros4CoopHalf {
         const bool ok = gj_invert_half<NP>(a, L, ord);
         const double ih = 1.0 / h;
         const double u1 = gj_apply_half<NP>(a, L, ord, f);
-        park(L, a);
         double ft = rhs<4>(M, L, y + Ros4::a21 * u1, P);
-        unpark(L, a);
         const double u2 = gj_apply_half<NP>(a, L, ord, ft + (Ros4::c21 * u1) * ih);
         ft = rhs<4>(M, L, y + Ros4::a31 * u1 + Ros4::a32 * u2, P);
-        unpark(L, a);
         const double u3 = gj_apply_half<NP>(a, L, ord, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
         const double u4 =
             gj_apply_half<NP>(a, L, ord, ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
