@@ -513,7 +513,12 @@ __device__ __forceinline__ void lu_factor(double (&a)[NP], LU<NP> &f) {
         const int p = __builtin_ctzll(__ballot(!done && key == mx));
         if (lane == k) f.pivv = p;
         f.ok = f.ok && (mx != 0ull);
-        const double inv = 1.0 / bcast(a[k], p);
+        // 1 / pivot: hardware reciprocal estimate refined by two Newton-Raphson steps (within an
+        // ulp; a shorter dependency chain than the correctly rounded division)
+        const double piv = bcast(a[k], p);
+        double inv = __builtin_amdgcn_rcp(piv);
+        inv = fma(fma(-piv, inv, 1.0), inv, inv);
+        inv = fma(fma(-piv, inv, 1.0), inv, inv);
         if (lane == p) {
             done = true;
             f.ord = k;
