@@ -35,11 +35,11 @@ TRAFFIC_REF = {
     "sources": ["paper_1608_05794_amd/csrc/k_wave.hip", "paper_1608_05794_amd/csrc/kinetics.h",
                 "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h",
                 "paper_1608_05794_amd/csrc/mech.hip"],
-    "sha256": "23406a764c030a3fa7dabb51cb1ccdb1739b0d9706d5395e3b5a47dc368e48a1",
+    "sha256": "222d8e4828ba45a2c867a89078be66ad3798b76872546cf45e0d7806630bd366",
     "args": {"mech": "M53", "reactors": 131072, "t_end": 1e-3, "kernel": "wave", "precision": "fp64",
              "launch_steps": 2000},
-    "fetch_kib_per_launch": 4031331986.76, "fetch_factor": 1048576.0 / 524302.5,
-    "write_kib_per_launch": 6247536145.86, "write_factor": 1.0,
+    "fetch_kib_per_launch": 687536.66, "fetch_factor": 1048576.0 / 524302.27,
+    "write_kib_per_launch": 370288869.13, "write_factor": 1.0,
 }
 TRANSCENDENTAL_FLOPS = 20           # FP64 operations charged per exp / log / log10 / exp10
 
