@@ -35,7 +35,7 @@ TRAFFIC_REF = {
     "sources": ["paper_1608_05794_amd/csrc/k_wave.hip", "paper_1608_05794_amd/csrc/kinetics.h",
                 "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h",
                 "paper_1608_05794_amd/csrc/mech.hip"],
-    "sha256": "222d8e4828ba45a2c867a89078be66ad3798b76872546cf45e0d7806630bd366",
+    "sha256": "0444d75f90944896969440a3d34f7d9e0af1ed11533442e74b531d8871c3ef8c",
     "args": {"mech": "M53", "reactors": 131072, "t_end": 1e-3, "kernel": "wave", "precision": "fp64",
              "launch_steps": 2000},
     "fetch_kib_per_launch": 687536.66, "fetch_factor": 1048576.0 / 524302.27,

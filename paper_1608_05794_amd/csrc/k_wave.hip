@@ -16,8 +16,7 @@
 #include "launch.h"
 
 extern "C" __device__ unsigned long long __ockl_wfred_max_u64(unsigned long long);
-extern "C" __device__ __forceinline__ double __ockl_wfred_add_f64(double);
-extern "C" __device__ unsigned int __ockl_wfred_max_u32(unsigned int);
+extern "C" __device__ double __ockl_wfred_add_f64(double);
 
 namespace ck {
 namespace {
