@@ -291,22 +291,25 @@ def _median_time(ck, torch, g, y, P, t_end, warmup=3, runs=5, **opts):
     return r, float(np.median(times))
 
 
-def _oracle_rate(path, y, P, t_end, n, threads, **kw):
+def cpu_baseline_rate(path, y, P, t_end, n, threads, **kw):
+    """CPU baseline leg of the suites: the oracle (ROS4) timed on the first n reactors with `threads`
+    host threads."""
     from oracle import oracle as O
     m = O.Mechanism(path)
     ys, Ps = np.ascontiguousarray(y[:, :n]), np.ascontiguousarray(P[:n])
     t0 = time.perf_counter()
     res = m.integrate(ys, Ps, t_end, "ros4", nthreads=threads, **kw)
     dt = time.perf_counter() - t0
-    return {"reactors": n, "threads": threads, "seconds": dt, "reactors_per_s": n / dt,
+    return {"kind": "oracle", "reactors": n, "cores": threads, "seconds": dt, "value": n / dt, "unit": "reactors/s",
             "mean_steps": float(np.mean(res["n_accept"] + res["n_reject"]))}
 
 
 def suite_methods(a):
     """The small configuration (13 species x 1024 reactors to 1e-4 s) with ROS4 and RKF45, a stiffness
-    census of its initial states, the oracle on all host cores and on one; the rate with host-to-device
-    and device-to-host transfers included; and ROS4 with the analytic Jacobian against forward
-    differences (53 species), with the oracle's one-core rate on the 53-species workload."""
+    census of its initial states, its CPU baseline (the oracle on all host cores and on one); the rate
+    with host-to-device and device-to-host transfers included; and ROS4 with the analytic Jacobian
+    against forward differences (53 species), with the one-core CPU baseline of the 53-species
+    workload."""
     import torch
 
     from paper_1608_05794_amd import ck, synth
@@ -335,8 +338,8 @@ def suite_methods(a):
     rho = np.abs(np.linalg.eigvals(J)).max(axis=1)
     small["stiffness_census"] = {"rho_percentiles_10_50_90": [float(v) for v in np.percentile(rho, [10, 50, 90])],
                                  "rkf45_steps_estimate_median": float(np.median(rho) * te / 3)}
-    small["oracle_all_cores"] = _oracle_rate(path, y0, P0, te, n, cores)
-    small["oracle_one_core"] = _oracle_rate(path, y0, P0, te, 128, 1)
+    small["cpu_baseline"] = {"all_cores": cpu_baseline_rate(path, y0, P0, te, n, cores),
+                             "one_core": cpu_baseline_rate(path, y0, P0, te, 128, 1)}
     # transfers included: pinned host state in, integrate, state / status / counters out
     hy = torch.empty(y0.shape, dtype=torch.float64, pin_memory=True)
     hy.copy_(torch.as_tensor(y0))
@@ -375,9 +378,9 @@ def suite_methods(a):
         print(f"methods jacobian {kind}: {dt:.2f} s", file=sys.stderr, flush=True)
     jac["analytic_speedup"] = jac["fd"]["seconds_median_of_3"] / jac["analytic"]["seconds_median_of_3"]
     out["jacobian"] = jac
-    # the oracle on one core for the headline workload's states (ROS4 to 1e-3 s)
+    # CPU baseline on one core for the headline workload's states (ROS4 to 1e-3 s)
     y0, P0 = synth.reactor_states(53, 4, "mid", seed=1002)
-    out["oracle_one_core_M53_1e-3"] = _oracle_rate(path, y0, P0, 1e-3, 4, 1)
+    out["cpu_baseline_one_core_M53_1e-3"] = cpu_baseline_rate(path, y0, P0, 1e-3, 4, 1)
     return out
 
 
