@@ -103,6 +103,10 @@ MECHS = {
     "M13": dict(nsp=13, nrxn=27, n_tb=4, n_troe=2, elements="HON", max_atoms=7, max_c=2, seed=13),
     "M53": dict(nsp=53, nrxn=325, n_tb=30, n_troe=25, elements="CHON", max_atoms=7, max_c=2, seed=53),
     "M111": dict(nsp=111, nrxn=784, n_tb=60, n_troe=40, elements="CHON", max_atoms=9, max_c=3, seed=111),
+    # test-only: many reactions per species (duplicates allowed), so the wavefront kernel's
+    # per-reaction scalars of the first Jacobian window do not fit its parking slice and the
+    # second window recomputes them
+    "M35X": dict(nsp=35, nrxn=900, n_tb=20, n_troe=10, elements="CHON", max_atoms=7, max_c=2, seed=35, dup=True),
 }
 
 
@@ -299,7 +303,7 @@ def _orient(species, left, right, t_ref=1200.0):
     return (left, right) if dg <= 0.0 else (right, left)
 
 
-def _build_reactions(rng, species, elements, nrxn, n_tb, n_troe):
+def _build_reactions(rng, species, elements, nrxn, n_tb, n_troe, dup=False):
     comps = [s.comp for s in species]
     exch, comb = _candidates(comps, elements)
     nsp = len(species)
@@ -329,6 +333,12 @@ def _build_reactions(rng, species, elements, nrxn, n_tb, n_troe):
             break
         if r not in chosen:
             chosen.append(r)
+    if dup:
+        # duplicate reactions (same stoichiometry, own rate expression), as real mechanisms have
+        k = 0
+        while len(chosen) < n_elem and pool:
+            chosen.append(pool[k % len(pool)])
+            k += 1
     if len(chosen) < n_elem or len(covered) < nsp:
         raise ValueError("candidate pool too small")
     reactions = []
@@ -380,6 +390,7 @@ def element_matrix(mech):
 
 def make_mechanism(name="M13", seed=None, hf_range=(-150e3, 150e3), s_range=(150.0, 350.0)):
     p = dict(MECHS[name])
+    dup = p.pop("dup", False)
     seed = p.pop("seed") if seed is None else seed
     elements = list(p["elements"])
     for attempt in range(50):
@@ -387,7 +398,7 @@ def make_mechanism(name="M13", seed=None, hf_range=(-150e3, 150e3), s_range=(150
         comps = _draw_species(rng, elements, p["nsp"], p["max_atoms"], p["max_c"])
         species = _make_species(rng, elements, comps, hf_range, s_range)
         try:
-            reactions = _build_reactions(rng, species, elements, p["nrxn"], p["n_tb"], p["n_troe"])
+            reactions = _build_reactions(rng, species, elements, p["nrxn"], p["n_tb"], p["n_troe"], dup)
         except ValueError:
             continue
         mech = Mechanism(elements, species, reactions)

@@ -158,6 +158,20 @@ def test_ros4_group_parity(ck, gmech, oracle_mech, name, n, te):
     _report_and_check(f"ros4 group {name}", res, orc)
 
 
+def test_ros4_second_window_recomputes_rates(ck, gmech, oracle_mech):
+    """35 species, 900 reactions (duplicates included): the per-reaction scalars of the first Jacobian
+    window (3 rows per 64 reactions, 45 rows) exceed the 40-row parking slice of N' = 40, so the
+    wavefront kernel's second window evaluates the rate constants again instead of reading them."""
+    g, om = gmech("M35X"), oracle_mech("M35X")
+    assert 3 * ((om.n_reactions + 63) // 64) > (om.N + 7) // 8 * 8
+    y, P = synth.reactor_states(om.n_species, 24, "mid", seed=1012)
+    f = ck.rhs(g, dev(y), dev(P), kernel="wave").cpu().numpy()
+    assert (np.abs(f - om.rhs(y, P)) / rhs_scale(om, y, P)).max() <= 1e-12
+    res, orc = _integrate_both(ck, g, om, y, P, 1e-8, "ros4", "wave")
+    assert np.array_equal(res["status"], orc["status"]) and np.all(orc["status"] == 0)
+    _report_and_check("ros4 M35X wave (second window recomputes)", res, orc)
+
+
 @pytest.mark.parametrize("method,kernel", [("ros4", "wave"), ("ros4", "lane"), ("ros4", "group"),
                                            ("rkf45", "wave"), ("rkf45", "lane")])
 def test_edge_cases(ck, gmech, oracle_mech, method, kernel):
