@@ -120,10 +120,11 @@ def parse():
     ap.add_argument("--rhs-batches", type=int, default=8, help="distinct state batches cycled in the RHS leg")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 8 per host core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--suite", default="integrate", choices=["integrate", "batching", "precision", "serving", "methods"],
+    ap.add_argument("--suite", default="integrate", choices=["integrate", "batching", "precision", "serving", "methods", "peaks"],
                     help="integrate: the headline line; batching / precision / serving: the three production "
                          "forms; methods: small configuration with both integrators, transfers, analytic vs "
-                         "forward-difference Jacobian (one JSON line each, bounded workloads)")
+                         "forward-difference Jacobian; peaks: achievable GEMM, FMA and copy rates (one "
+                         "JSON line each, bounded workloads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (counter calibration) and exit")
     return ap.parse_args()
@@ -384,6 +385,44 @@ def suite_methods(a):
     return out
 
 
+def suite_peaks(a):
+    """Achievable rates on this GPU, for context beside the published peaks the roofline uses: FP64
+    GEMM (the library path, matrix units), an elementwise FP64 FMA over resident data (vector units,
+    memory-bound by construction), and a device-to-device copy of 1 GiB (STREAM-like)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    out = {"suite": "peaks", "published": {"fp64_vector_tflops": 78.6, "fp64_matrix_tflops": 78.6, "hbm_tbps": 8.0}}
+    n = 8192
+    A = torch.randn(n, n, dtype=torch.float64, device=dev)
+    B = torch.randn(n, n, dtype=torch.float64, device=dev)
+    C = torch.empty_like(A)
+    dt = timed(lambda: torch.matmul(A, B, out=C), 5)
+    out["fp64_gemm_tflops"] = 2.0 * n ** 3 / dt / 1e12
+    del A, B, C
+    m = (1 << 30) // 8
+    x = torch.ones(m, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    dt = timed(lambda: y.copy_(x), 10)
+    out["copy_gbps"] = 2.0 * m * 8 / dt / 1e9
+    # y = x + x * x: the three operands alias one tensor, so HBM sees one read and one write stream
+    dt = timed(lambda: torch.addcmul(x, x, x, value=1.0, out=y), 10)
+    out["fp64_fma_elementwise"] = {"tflops": 2.0 * m / dt / 1e12, "gbps": 2.0 * m * 8 / dt / 1e9}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -394,7 +433,7 @@ def main():
 
     if a.suite != "integrate":
         fn = {"batching": suite_batching, "precision": suite_precision, "serving": suite_serving,
-              "methods": suite_methods}[a.suite]
+              "methods": suite_methods, "peaks": suite_peaks}[a.suite]
         print(json.dumps(fn(a)), flush=True)
         return
 
