@@ -2,14 +2,15 @@
 
 Requests (a mechanism, a batch of reactor states, pressures and an end time)
 are admitted into device-resident slot pools, one pool per mechanism, under
-an HBM budget.  The service runs iterations: in each iteration every pool
-with active slots gets one bounded launch of the wavefront work-queue
-integrator (at most `launch_steps` attempted steps per reactor), each pool on
-its own stream so the mechanisms' work overlaps on the device.  Reactors
-resume from their (t, h) in the next iteration, so a request's result does
-not depend on how its work was split into launches or what else was in the
-pool.  A request completes when none of its reactors still has steps left;
-its slots are freed and waiting requests are admitted at the next iteration.
+an HBM budget.  Each pool with active slots runs bounded launches of the
+persistent work-queue integrator (at most `launch_steps` attempted steps per
+reactor) on its own stream, so the mechanisms' work overlaps on the device,
+and each pool is harvested and relaunched as soon as its own launch ends
+(a completion event per launch), not at the pace of the slowest pool.
+Reactors resume from their (t, h) in the next launch, so a request's result
+does not depend on how its work was split into launches or what else was in
+the pool.  A request completes when none of its reactors still has steps
+left; its slots are freed and waiting requests are admitted.
 
 Only the control plane is here (admission, slot bookkeeping, timing); every
 state update runs in the library's kernels.
@@ -38,6 +39,7 @@ class Request:
     admitted: float = -1.0
     completed: float = -1.0
     slots: tuple = ()         # (start, stop) in its pool
+    launched: bool = False    # part of a launch whose statuses have not been read yet
     result: dict = field(default_factory=dict)
 
     @property
@@ -71,6 +73,7 @@ class Pool:
         self.active = {}                                     # rid -> Request
         self.hwm = 0                                         # slots beyond it are empty
         self.last = None
+        self.event = None
 
     # --- slot bookkeeping ----------------------------------------------------------------
     def bytes_per_reactor(self):
@@ -118,26 +121,44 @@ class Pool:
     def launch(self):
         if not self.active or self.hwm == 0:
             self.last = None
+            self.event = None
             return
         n = self.hwm
+        for req in self.active.values():
+            req.launched = True
         with torch.cuda.stream(self.stream):
             r = ck.integrate(self.mech, self.y[:, :n], self.P[:n], self.te[:n], method=self.method,
                              t=self.t[:n], h=self.h[:n], workspace=self.ws, stream=self.stream, inplace=True,
                              max_steps=self.launch_steps, **self.opts)
             self.steps[:n].add_(r["n_accept"] + r["n_reject"])
             self.last = r["status"]
+            self.event = torch.cuda.Event()
+            self.event.record(self.stream)
+
+    def in_flight(self):
+        return self.event is not None
+
+    def finished(self):
+        """The last launch (and the bookkeeping queued behind it) has completed on the device."""
+        return self.event is not None and self.event.query()
 
     def harvest(self, now):
-        """Requests whose reactors all finished; frees their slots."""
+        """Requests of the last launch whose reactors all finished; frees their slots.  Requests
+        admitted while that launch ran were not part of it and wait for the next one."""
         done = []
+        self.event = None
         if self.last is None:
             return done
-        unfinished = (self.last == ST_MAX_STEPS).cpu().numpy()
+        last, self.last = self.last, None
+        unfinished = (last == ST_MAX_STEPS).cpu().numpy()
         for rid, req in list(self.active.items()):
+            if not req.launched:
+                continue
+            req.launched = False
             a, b = req.slots
             if not unfinished[a:b].any():
                 req.completed = now
-                req.result = dict(y=self.y[:, a:b].cpu().numpy(), status=self.last[a:b].cpu().numpy(),
+                req.result = dict(y=self.y[:, a:b].cpu().numpy(), status=last[a:b].cpu().numpy(),
                                   steps=self.steps[a:b].cpu().numpy())
                 del self.active[rid]
                 self.release(a, b)
@@ -163,7 +184,7 @@ class Server:
         """Serve `requests` (sorted by arrival) against the wall clock; returns completed requests."""
         pending = list(requests)
         t0 = time.perf_counter()
-        while pending or self.waiting or any(p.active for p in self.pools.values()):
+        while pending or self.waiting or any(p.active or p.in_flight() for p in self.pools.values()):
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
                 self.waiting.append(pending.pop(0))
@@ -176,20 +197,24 @@ class Server:
                 req.admitted = time.perf_counter() - t0
                 self.used += cost
                 self.waiting.pop(0)
-            if not any(p.active for p in self.pools.values()):
+            if not any(p.active or p.in_flight() for p in self.pools.values()):
                 if pending:
                     time.sleep(max(0.0, min(pending[0].arrival - now, 0.01)))
                 continue
             for p in self.pools.values():
-                p.launch()
+                if p.active and not p.in_flight():
+                    p.launch()
+            harvested = False
             for p in self.pools.values():
-                p.stream.synchronize()
-            self.iterations += 1
-            now = time.perf_counter() - t0
-            for p in self.pools.values():
-                for req in p.harvest(now):
-                    self.used -= self._cost(req)
-                    self.done.append(req)
+                if p.finished():
+                    self.iterations += 1
+                    harvested = True
+                    now = time.perf_counter() - t0
+                    for req in p.harvest(now):
+                        self.used -= self._cost(req)
+                        self.done.append(req)
+            if not harvested:
+                time.sleep(0.0002)
             if log and self.iterations % 20 == 0:
                 log(f"iteration {self.iterations}: t={now:.1f}s done {len(self.done)} waiting {len(self.waiting)} "
                     f"active {sum(len(p.active) for p in self.pools.values())}")
