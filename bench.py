@@ -4,10 +4,14 @@ Workload (mid configuration): synthetic 53-species / 325-reaction mechanism
 (30 third-body, 25 Troe), 131072 constant-pressure reactors with
 T0 ~ U(900, 1800) K, P ~ U(1, 20) atm, Y0 ~ Dirichlet(0.5), integrated with
 ROS4 to t = 1e-3 s at rtol 1e-8, atol 1e-12, FP64.  One "step" integrates the
-whole batch from its initial state; inputs are resident in HBM before the
-timed region.  Also reported: source-term (RHS) evaluations per second over
-distinct state batches, the roofline of the dominant kernel, and the CPU
-oracle on a bounded sample of the same workload.
+whole batch from its initial state (about two minutes on one MI355X); inputs
+are resident in HBM before the timed region.  --steps and --warmup are upper
+limits: the run keeps to a wall-clock budget (--budget-s, counted from process
+start), times at least one step and as many more as fit, and reports the
+numbers it actually ran.  A warm-up pass is one bounded launch (a few attempted
+steps per reactor over the whole batch).  Also reported: source-term (RHS)
+evaluations per second over distinct state batches, the roofline of the
+dominant kernel, and the CPU oracle on a bounded sample of the same workload.
 
 Prints one JSON line (rank 0).  Only one GPU is used; --gpus > 1 exits.
 """
@@ -16,6 +20,8 @@ import json
 import os
 import sys
 import time
+
+T_PROCESS_START = time.time()   # the wall budget of the headline leg counts from here
 
 import numpy as np
 
@@ -118,13 +124,24 @@ def parse():
     ap.add_argument("--max-steps", type=int, default=1_000_000, help="attempted steps per reactor in total")
     ap.add_argument("--rhs-evals", type=int, default=100, help="RHS evaluations per reactor in the RHS leg")
     ap.add_argument("--rhs-batches", type=int, default=8, help="distinct state batches cycled in the RHS leg")
-    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 8 per host core)")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 8 per host thread)")
+    ap.add_argument("--budget-s", type=float, default=450.0,
+                    help="wall-clock budget of the headline run, from process start: timed steps stop once "
+                         "another would not fit before the RHS and CPU legs (at least one step is timed)")
+    ap.add_argument("--warmup-launch-steps", type=int, default=16,
+                    help="attempted steps per reactor of one warm-up pass (a single bounded launch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--suite", default="integrate", choices=["integrate", "batching", "precision", "serving", "methods", "peaks"],
                     help="integrate: the headline line; batching / precision / serving: the three production "
                          "forms; methods: small configuration with both integrators, transfers, analytic vs "
                          "forward-difference Jacobian; peaks: achievable GEMM, FMA and copy rates (one "
                          "JSON line each, bounded workloads)")
+    ap.add_argument("--serve-requests", type=int, default=32, help="serving suite: arrivals served")
+    ap.add_argument("--serve-t-scale", type=float, default=1e-3, help="serving suite: factor on drawn end times")
+    ap.add_argument("--serve-time-limit", type=float, default=150.0, help="serving suite: wall time limit (s)")
+    ap.add_argument("--serve-launch-steps", type=int, default=400, help="serving suite: attempted steps per launch")
+    ap.add_argument("--serve-precision", default="fp64", choices=["fp64", "fp32_refine"],
+                    help="serving suite: linear-solve precision of the pools that support it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (counter calibration) and exit")
     return ap.parse_args()
@@ -146,10 +163,20 @@ def measured_traffic(a):
             ref["write_kib_per_launch"] * 1024 * ref["write_factor"])
 
 
+def host_threads():
+    """Host threads for the oracle: the CPUs this process may run on, capped by OMP_NUM_THREADS when it
+    is set (a GPU host may expose more cores than its share)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return n
+
+
 def cpu_baseline(path, y, P, t_end, sample):
     """The CPU oracle (one reactor per OpenMP task, dynamic schedule) on a bounded sample."""
     from oracle import oracle as O
-    cores = len(os.sched_getaffinity(0))
+    cores = host_threads()
     sample = sample or 8 * cores
     sample = min(sample, y.shape[1])
     m = O.Mechanism(path)
@@ -258,27 +285,46 @@ def suite_precision(a):
 
 
 def suite_serving(a):
-    """Continuous batching: a Poisson request stream (2000 requests/s offered; mechanisms 13 / 53 / 111
-    species with weights 0.3 / 0.5 / 0.2; reactor count and end time log-uniform) served under a 200 GB
-    HBM budget; completed-request latency p50 / p99 and throughput.  Bounded: 64 requests with at most
-    2048 reactors and end times 1e-8 to 1e-6 s."""
+    """Continuous batching on the configured request stream: Poisson arrivals at 2000 requests/s,
+    mechanisms of 13 / 53 / 111 species with weights 0.3 / 0.5 / 0.2, reactor counts log-uniform in
+    1..65536 and end times log-uniform in 1e-6..1e-3 s, states as in the other configurations,
+    admitted into device-resident slot pools sized from a 200 GB HBM budget.  Bounded: the first
+    --serve-requests arrivals of the stream, end times multiplied by --serve-t-scale, and a wall
+    time limit; requests unfinished at the limit are reported as backlog.  Reports offered and
+    served load and completed-request latency p50 / p99 (arrival to completion)."""
     import torch
 
     from paper_1608_05794_amd import ck, serve, synth
     mechs = {m: ck.Mechanism(synth.mechanism_file(m)) for m in ("M13", "M53", "M111")}
     species = {m: g.n_species for m, g in mechs.items()}
-    reqs = serve.poisson_requests(64, 2000.0, seed=5000, n_range=(1, 2048), t_range=(1e-8, 1e-6), species=species)
-    srv = serve.Server(mechs, capacity={"M13": 16384, "M53": 16384, "M111": 8192}, hbm_budget=200e9,
-                       launch_steps=400)
+    reqs = serve.poisson_requests(a.serve_requests, 2000.0, seed=5000, n_range=(1, 65536), t_range=(1e-6, 1e-3),
+                                  species=species)
+    for r in reqs:
+        r.t_end *= a.serve_t_scale
+    pool_opts = {}
+    if a.serve_precision != "fp64":
+        pool_opts = {m: {"precision": a.serve_precision} for m in ("M13", "M53")}
+    srv = serve.Server(mechs, hbm_budget=200e9, launch_steps=a.serve_launch_steps, pool_opts=pool_opts)
+    by_mech = {m: sum(1 for r in reqs if r.mech == m) for m in mechs}
     t0 = time.perf_counter()
-    done = srv.run(reqs, time_limit=240.0, log=lambda m: print(m, file=sys.stderr, flush=True))
-    el = time.perf_counter() - t0
+    done = srv.run(reqs, time_limit=a.serve_time_limit, log=lambda m: print(m, file=sys.stderr, flush=True))
     torch.cuda.synchronize()
-    summ = serve.latency_summary(done, 2000.0, el)
-    return {"suite": "serving", "requests": len(reqs), "completed": len(done), "elapsed_s": el,
-            "iterations": srv.iterations, "reactors": sum(r.n for r in reqs), **summ,
-            "stream": "64 requests, Poisson 2000/s, mechanisms 0.3/0.5/0.2, reactors log-uniform 1-2048, "
-                      "t_end log-uniform 1e-8-1e-6 s, 200 GB budget"}
+    el = time.perf_counter() - t0
+    summ = serve.latency_summary(done, 2000.0, el, arrived=reqs)
+    lat = {m: [r.completed - r.arrival for r in done if r.mech == m] for m in mechs}
+    steps = {m: float(np.mean(np.concatenate([r.result["steps"] for r in done if r.mech == m])))
+             for m in mechs if any(r.mech == m for r in done)}
+    return {"suite": "serving", "data": "synthetic", "dtype": "f64",
+            "stream": f"first {len(reqs)} arrivals (seed 5000) of Poisson 2000/s, mechanisms 0.3/0.5/0.2 over "
+                      f"13/53/111 species, reactors log-uniform 1-65536, t_end log-uniform 1e-6-1e-3 s "
+                      f"x {a.serve_t_scale:g}, 200 GB budget",
+            "requests": len(reqs), "requests_by_mechanism": by_mech, "reactors_offered": sum(r.n for r in reqs),
+            "elapsed_s": el, "time_limit_s": a.serve_time_limit, "iterations": srv.iterations,
+            "backlog_at_end": srv.backlog(), "max_backlog": srv.max_backlog, "rejected": len(srv.rejected),
+            "pool_capacity": {m: p.cap for m, p in srv.pools.items()}, "allocated_bytes": srv.allocated,
+            "precision": a.serve_precision, "launch_steps": a.serve_launch_steps,
+            "p50_s_by_mechanism": {m: float(np.percentile(v, 50)) for m, v in lat.items() if v},
+            "mean_attempted_steps_by_mechanism": steps, **summ}
 
 
 def _median_time(ck, torch, g, y, P, t_end, warmup=3, runs=5, **opts):
@@ -495,20 +541,47 @@ def main():
             if left == 0 or launches * a.launch_steps >= a.max_steps:
                 return r, kern, launches
 
+    def elapsed():
+        return time.time() - T_PROCESS_START
+
+    # Warm-up passes (untimed): one bounded launch each over the whole batch from its initial state,
+    # which loads the code objects and touches the workspace without a full two-minute integration.
+    warm = 0
     for i in range(a.warmup):
-        one_step(f"warmup {i}")
-    torch.cuda.synchronize()
-    kern_s = []
+        yw.copy_(y0d)
+        tt.zero_()
+        hh.zero_()
+        ck.integrate(g, yw, Pd, ted, method="ros4", t=tt, h=hh, workspace=ws, inplace=True, kernel=a.kernel,
+                     precision=a.precision, max_steps=a.warmup_launch_steps)
+        torch.cuda.synchronize()
+        warm += 1
+    print(f"warm-up: {warm} passes of {a.warmup_launch_steps} attempted steps, {elapsed():.1f} s since start",
+          file=sys.stderr, flush=True)
+
+    # Timed steps: at least one; another only if it fits the budget with the RHS and CPU legs after it.
+    reserve_s = 15.0 + (0.0 if a.no_cpu_baseline else 45.0)
+    kern_s, walls, launches_l = [], [], []
     t0 = time.perf_counter()
     for i in range(a.steps):
+        if walls and elapsed() + max(walls) + reserve_s > a.budget_s:
+            print(f"budget: stopping after {len(walls)} timed steps ({elapsed():.1f} s since start, "
+                  f"budget {a.budget_s:.0f} s)", file=sys.stderr, flush=True)
+            break
+        s0 = time.perf_counter()
         r, kern, launches = one_step(f"step {i}")
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - s0)
         kern_s.append(kern)
+        launches_l.append(launches)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    timing_end_s = elapsed()
+    n_steps = len(walls)
     steps = acc_steps.to(torch.float64)
     status = torch.bincount(r["status"].to(torch.int64), minlength=4).tolist()
     total_steps = float(steps.sum().item())
-    kernel_s = sum(kern_s) / len(kern_s)
+    kernel_s = sum(kern_s) / n_steps
+    launches = launches_l[-1]
     flops_launch = total_steps * fl["ros4_step"] + a.reactors * fl["h0"]
     achieved = flops_launch / kernel_s
 
@@ -539,12 +612,12 @@ def main():
 
     res = {
         "metric": METRIC,
-        "value": a.reactors * a.steps / wall,
+        "value": a.reactors * n_steps / wall,
         "unit": "reactors/s",
         "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": 1e3 * wall / a.steps,
+        "steps": n_steps,
+        "warmup": warm,
+        "ms_per_step": 1e3 * wall / n_steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -552,11 +625,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.mech} x {a.reactors} reactors, ROS4 to {a.t_end:g} s, rtol 1e-8, atol 1e-12",
                    "mechanism": f"{a.mech} ({info['n_species']} species, {len(info['reactions'])} reactions)",
-                   "reactors": a.reactors, "t_end": a.t_end, "kernel": a.kernel, "precision": a.precision},
+                   "reactors": a.reactors, "t_end": a.t_end, "kernel": a.kernel, "precision": a.precision,
+                   "step": "integrate the whole batch from its initial state to t_end",
+                   "warmup_pass": f"one launch of {a.warmup_launch_steps} attempted steps per reactor",
+                   "steps_requested": a.steps, "warmup_requested": a.warmup, "budget_s": a.budget_s},
         "rhs_evals_per_s": rhs_rate,
         "rhs_evals_per_s_lane_kernel": rhs_rate_lane,
         "mean_steps_per_reactor": total_steps / a.reactors,
         "launches_per_step": launches,
+        "step_seconds": walls,
+        "wall_s_since_start_at_end_of_timing": timing_end_s,
         "status_counts": {"ok": status[0], "max_steps": status[1], "h_underflow": status[2], "nonfinite": status[3]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": measured_traffic(a),

@@ -88,6 +88,17 @@ def _state(y, N):
     return y.stride(0)
 
 
+def _vec(v, n, dev, name, dtype=torch.float64):
+    """Check a per-reactor vector argument: `dtype`, on the state's device, stride 1, >= n entries."""
+    if v is None:
+        return None
+    if not torch.is_tensor(v) or v.dtype != dtype or v.device != dev or v.dim() != 1:
+        raise CkError(f"{name} must be a 1-d {dtype} tensor on {dev}")
+    if v.numel() < n or (v.numel() > 1 and v.stride(0) != 1):
+        raise CkError(f"{name} must be contiguous with at least {n} entries")
+    return v
+
+
 def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000, kernel="auto", precision="fp64",
               refine_sweeps=3, blocks_per_cu=0, jacobian="analytic", reactor="cp"):
     o = Opts()
@@ -140,9 +151,11 @@ def rhs(mech, y, p, out=None, kernel=None, stream=None, reactor="cp"):
     for reactor="cp", densities (kg/m^3) for "cv"."""
     ld = _state(y, mech.N)
     n = y.shape[1]
+    _vec(p, n, y.device, "p")
     out = torch.empty_like(y) if out is None else out
-    if out.stride(0) != ld or out.stride(1) != 1:
-        raise CkError("output must have the state's strides")
+    if out.dtype != torch.float64 or out.device != y.device or out.shape != y.shape or \
+            out.stride(0) != ld or out.stride(1) != 1:
+        raise CkError("output must be a float64 tensor with the state's shape, device and strides")
     if kernel is None and reactor == "cp":
         _check(lib().ck_rhs_eval(mech.handle, n, _ptr(y), ld, _ptr(p), _ptr(out), _stream(stream)))
     else:
@@ -153,8 +166,13 @@ def rhs(mech, y, p, out=None, kernel=None, stream=None, reactor="cp"):
 
 def jac(mech, y, p, kernel=None, stream=None, reactor="cp"):
     """Analytic Jacobian (ck_jacobian_eval / _ex): returns [N*N, n] with row (i*N + j) = df_i/dy_j."""
-    ld = _state(y, mech.N)
+    _state(y, mech.N)
     n = y.shape[1]
+    _vec(p, n, y.device, "p")
+    # the library writes jac[(i N + j) ld + r] with the state's leading dimension: pass a compact state
+    # so that ld = n matches the [N*N, n] output
+    y = y.contiguous()
+    ld = _state(y, mech.N)
     out = torch.empty((mech.N * mech.N, n), dtype=torch.float64, device=y.device)
     if kernel is None and reactor == "cp":
         _check(lib().ck_jacobian_eval(mech.handle, n, _ptr(y), ld, _ptr(p), _ptr(out), _stream(stream)))
@@ -171,15 +189,26 @@ def integrate(mech, y, p, t_end, method="ros4", t=None, h=None, workspace=None, 
     Returns dict(y, t, h, status, n_accept, n_reject) of device tensors.  t and h
     (float64 [n]) are updated in place when given, so a later call resumes exactly.
     """
-    ld = _state(y, mech.N)
+    _state(y, mech.N)
     n = y.shape[1]
     dev = y.device
-    yy = y if inplace else y.clone()
+    # a copy is compact whatever the input's strides: take the leading dimension from what is passed
+    yy = y if inplace else y.clone(memory_format=torch.contiguous_format)
+    ld = _state(yy, mech.N)
+    _vec(p, n, dev, "p")
+    _vec(t, n, dev, "t")
+    _vec(h, n, dev, "h")
     te = t_end if torch.is_tensor(t_end) else torch.full((n,), float(t_end), dtype=torch.float64, device=dev)
+    _vec(te, n, dev, "t_end")
     st = torch.empty(n, dtype=torch.int32, device=dev)
     na = torch.empty(n, dtype=torch.int32, device=dev)
     nr = torch.empty(n, dtype=torch.int32, device=dev)
     o = make_opts(**opts)
+    if workspace is not None:
+        need = int(lib().ck_workspace_bytes(mech.handle, n, C.byref(o)))
+        if not torch.is_tensor(workspace) or workspace.device != dev or not workspace.is_contiguous() or \
+                workspace.numel() * workspace.element_size() < need:
+            raise CkError(f"workspace must be a contiguous tensor on {dev} of at least {need} bytes")
     fn = {"ros4": lib().ck_integrate_ros4, "rkf45": lib().ck_integrate_rkf45}[method]
     _check(fn(mech.handle, n, _ptr(yy), ld, _ptr(p), _ptr(te), _ptr(t), _ptr(h), C.byref(o), _ptr(workspace),
               _ptr(st), _ptr(na), _ptr(nr), _stream(stream)))

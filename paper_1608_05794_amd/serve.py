@@ -12,6 +12,17 @@ does not depend on how its work was split into launches or what else was in
 the pool.  A request completes when none of its reactors still has steps
 left; its slots are freed and waiting requests are admitted.
 
+HBM budget: the pools are the serving state's device memory.  Unless capacities
+are given, each pool's capacity is its share of the budget divided by the bytes
+one reactor slot holds (state, pressure, end time, t, h, step counters, and
+its share of the integrator workspace), capped at `max_capacity` slots so a
+launch never sweeps an unbounded grid; the pools' real allocations are checked
+against the budget at construction.  A request is admitted when its pool has
+a free range of slots for all its reactors; one that is larger than its
+pool's capacity can never be admitted and is rejected on arrival.  Each
+mechanism has its own FIFO queue, so a request that waits for slots holds up
+only later requests of the same mechanism.
+
 Only the control plane is here (admission, slot bookkeeping, timing); every
 state update runs in the library's kernels.
 """
@@ -41,6 +52,7 @@ class Request:
     slots: tuple = ()         # (start, stop) in its pool
     launched: bool = False    # part of a launch whose statuses have not been read yet
     result: dict = field(default_factory=dict)
+    error: str = ""           # set when the request was rejected (never admitted)
 
     @property
     def n(self):
@@ -76,8 +88,18 @@ class Pool:
         self.event = None
 
     # --- slot bookkeeping ----------------------------------------------------------------
+    @staticmethod
+    def slot_bytes(N):
+        """Device bytes of one reactor slot: state [N], P, t_end, t, h (float64) and the step counter."""
+        return (N + 4) * 8 + 8
+
+    def device_bytes(self):
+        """Device memory this pool holds (its arrays and the integrator workspace)."""
+        ts = (self.y, self.P, self.te, self.t, self.h, self.steps, self.ws)
+        return sum(t.numel() * t.element_size() for t in ts)
+
     def bytes_per_reactor(self):
-        return (self.mech.N + 6) * 8 + self.ws.numel() // max(self.cap, 1)
+        return self.device_bytes() / max(self.cap, 1)
 
     def alloc(self, n):
         for i, (a, b) in enumerate(self.free):
@@ -167,36 +189,67 @@ class Pool:
 
 
 class Server:
-    """Admission by HBM budget and continuous batching over per-mechanism pools."""
+    """Admission by HBM budget and continuous batching over per-mechanism pools.
 
-    def __init__(self, mechs: dict, capacity: dict, hbm_budget=200e9, launch_steps=500, **opts):
-        self.pools = {k: Pool(m, capacity[k], launch_steps=launch_steps, **opts) for k, m in mechs.items()}
-        self.budget = hbm_budget
-        self.used = 0.0
-        self.waiting = []
+    mechs: name -> ck.Mechanism.  capacity: name -> slots (default: the budget split evenly over
+    the mechanisms, capped at max_capacity).  pool_opts: name -> extra integrator options for that
+    pool (for example {"precision": "fp32_refine"}); opts apply to every pool."""
+
+    def __init__(self, mechs: dict, capacity: dict = None, hbm_budget=200e9, launch_steps=500,
+                 max_capacity=262144, pool_opts: dict = None, **opts):
+        self.budget = float(hbm_budget)
+        pool_opts = pool_opts or {}
+        if capacity is None:
+            share = self.budget / max(len(mechs), 1)
+            capacity = {}
+            for k, m in mechs.items():
+                o = dict(opts, **pool_opts.get(k, {}))
+                fixed = m.workspace_bytes(1, **o)
+                slots = int((share - fixed) // Pool.slot_bytes(m.N))
+                capacity[k] = max(0, min(max_capacity, slots)) // 64 * 64
+        self.pools = {k: Pool(m, capacity[k], launch_steps=launch_steps, **dict(opts, **pool_opts.get(k, {})))
+                      for k, m in mechs.items()}
+        self.allocated = sum(p.device_bytes() for p in self.pools.values())
+        if self.allocated > self.budget:
+            raise ValueError(f"pools need {self.allocated:.3e} B of device memory, over the {self.budget:.3e} B budget")
+        self.waiting = {k: [] for k in mechs}     # per-mechanism FIFO queues
         self.done = []
+        self.rejected = []
         self.iterations = 0
+        self.max_backlog = 0
 
-    def _cost(self, req):
-        return req.n * self.pools[req.mech].bytes_per_reactor()
+    def backlog(self):
+        """Requests that arrived and are not finished: waiting for slots or on the device."""
+        return sum(len(q) for q in self.waiting.values()) + sum(len(p.active) for p in self.pools.values())
+
+    def _arrive(self, req, now):
+        pool = self.pools.get(req.mech)
+        if pool is None or req.n > pool.cap or req.n < 1:
+            req.error = "unknown mechanism" if pool is None else f"{req.n} reactors do not fit a pool of {pool.cap}"
+            req.completed = now
+            self.rejected.append(req)
+        else:
+            self.waiting[req.mech].append(req)
 
     def run(self, requests, time_limit=None, log=None):
-        """Serve `requests` (sorted by arrival) against the wall clock; returns completed requests."""
+        """Serve `requests` (sorted by arrival) against the wall clock; returns completed requests.
+        Stops early once `time_limit` seconds have passed (requests still waiting or on the device
+        are then counted in `backlog()`)."""
         pending = list(requests)
         t0 = time.perf_counter()
-        while pending or self.waiting or any(p.active or p.in_flight() for p in self.pools.values()):
+        next_log = 0
+        while pending or self.backlog() or any(p.in_flight() for p in self.pools.values()):
             now = time.perf_counter() - t0
+            if time_limit is not None and now > time_limit:
+                break
             while pending and pending[0].arrival <= now:
-                self.waiting.append(pending.pop(0))
-            # FIFO admission under the HBM budget and slot capacity
-            while self.waiting:
-                req = self.waiting[0]
-                cost = self._cost(req)
-                if self.used + cost > self.budget or not self.pools[req.mech].admit(req):
-                    break
-                req.admitted = time.perf_counter() - t0
-                self.used += cost
-                self.waiting.pop(0)
+                self._arrive(pending.pop(0), now)
+            # admission: each mechanism's queue in arrival order, while its pool has room
+            for k, q in self.waiting.items():
+                while q and self.pools[k].admit(q[0]):
+                    q[0].admitted = time.perf_counter() - t0
+                    q.pop(0)
+            self.max_backlog = max(self.max_backlog, self.backlog())
             if not any(p.active or p.in_flight() for p in self.pools.values()):
                 if pending:
                     time.sleep(max(0.0, min(pending[0].arrival - now, 0.01)))
@@ -210,16 +263,14 @@ class Server:
                     self.iterations += 1
                     harvested = True
                     now = time.perf_counter() - t0
-                    for req in p.harvest(now):
-                        self.used -= self._cost(req)
-                        self.done.append(req)
+                    self.done.extend(p.harvest(now))
             if not harvested:
                 time.sleep(0.0002)
-            if log and self.iterations % 20 == 0:
-                log(f"iteration {self.iterations}: t={now:.1f}s done {len(self.done)} waiting {len(self.waiting)} "
-                    f"active {sum(len(p.active) for p in self.pools.values())}")
-            if time_limit and now > time_limit:
-                break
+            if log and self.iterations >= next_log:
+                next_log = self.iterations + 20
+                log(f"iteration {self.iterations}: t={now:.1f}s done {len(self.done)} "
+                    f"waiting {sum(len(q) for q in self.waiting.values())} "
+                    f"active {sum(len(p.active) for p in self.pools.values())} rejected {len(self.rejected)}")
         return self.done
 
 
@@ -248,11 +299,17 @@ def poisson_requests(n_requests, rate, seed=5000, mech_weights=(("M13", 0.3), ("
     return out
 
 
-def latency_summary(done, offered_rate, elapsed):
+def latency_summary(done, offered_rate, elapsed, arrived=None):
+    """Completed-request latency (arrival to completion) and served load over `elapsed` seconds."""
     lat = np.array([r.completed - r.arrival for r in done]) if done else np.zeros(0)
     reactors = sum(r.n for r in done)
-    return dict(completed=len(done), offered_rate=offered_rate,
-                served_rate=len(done) / elapsed if elapsed > 0 else 0.0,
-                reactors_per_s=reactors / elapsed if elapsed > 0 else 0.0,
-                p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
-                p99_s=float(np.percentile(lat, 99)) if len(lat) else None)
+    out = dict(completed=len(done), offered_rate=offered_rate,
+               served_rate=len(done) / elapsed if elapsed > 0 else 0.0,
+               reactors_per_s=reactors / elapsed if elapsed > 0 else 0.0,
+               p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
+               p99_s=float(np.percentile(lat, 99)) if len(lat) else None)
+    if arrived is not None:
+        out["arrived"] = len(arrived)
+        out["offered_reactors_per_s"] = (sum(r.n for r in arrived) / (max(r.arrival for r in arrived) or 1e-9)
+                                         if arrived else 0.0)
+    return out

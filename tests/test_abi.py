@@ -57,3 +57,22 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(ck, "_lib", None)
     with pytest.raises(ck.CkError):
         ck.lib()
+
+
+def test_binding_vector_checks():
+    """The binding's per-reactor vector checks (host tensors stand in for device ones here)."""
+    import torch
+
+    from paper_1608_05794_amd import ck
+    cpu = torch.device("cpu")
+    v = torch.zeros(8, dtype=torch.float64)
+    assert ck._vec(v, 8, cpu, "p") is v
+    assert ck._vec(None, 8, cpu, "t") is None
+    with pytest.raises(ck.CkError):
+        ck._vec(v, 9, cpu, "p")                               # too short
+    with pytest.raises(ck.CkError):
+        ck._vec(v.to(torch.float32), 8, cpu, "p")             # wrong dtype
+    with pytest.raises(ck.CkError):
+        ck._vec(torch.zeros(16, dtype=torch.float64)[::2], 8, cpu, "p")   # strided
+    with pytest.raises(ck.CkError):
+        ck._vec(torch.zeros(2, 8, dtype=torch.float64), 8, cpu, "p")      # not a vector

@@ -238,3 +238,18 @@ def test_lu_against_scipy():
         assert np.allclose(x, ref, rtol=1e-10, atol=1e-12)
     with pytest.raises(ArithmeticError):
         O.lu_solve(np.zeros((3, 3)), np.ones(3))
+
+
+def test_golden_stability_values_are_reproducible():
+    """stability_values.json is exactly what its generator derives from the printed tables."""
+    import importlib.util
+    path = os.path.join(os.path.dirname(__file__), "golden", "make_stability_values.py")
+    spec = importlib.util.spec_from_file_location("make_stability_values", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    assert mod.values() == GOLD
+    # the exact rationals behind the floats: b matches exp(z) through z^4, z^5 coefficient 1/104
+    sol, err = mod.rkf45_polys()
+    from fractions import Fraction as Fr
+    assert sol == [Fr(1), Fr(1), Fr(1, 2), Fr(1, 6), Fr(1, 24), Fr(1, 104)]
+    assert err == [0, 0, 0, 0, 0, Fr(-1, 780), Fr(1, 2080)]

@@ -129,3 +129,47 @@ def test_isomerization_closed_form(kind, method, tmp_path):
     YA = res["y"][1, 0]
     assert YA == pytest.approx(_closed_form_YA(y, P, mech, kf, kr, t_end), rel=2e-9)
     assert res["y"][0, 0] == pytest.approx(T, rel=1e-12)
+
+
+# Troe broadening (Gilbert, Luther & Troe 1983, the standard fall-off form the paper defers to):
+# log10 F = log10 Fc / (1 + f^2), f = x / (n - 0.14 x), x = log10 Pr + c, c = -0.4 - 0.67 log10 Fc,
+# n = 0.75 - 1.27 log10 Fc, Fc = (1 - a) exp(-T/T***) + a exp(-T/T*) + exp(-T**/T).
+# Points where F is known without evaluating that expression: x = 0 (f = 0, F = Fc), x = n / 1.14
+# (f = +1, F = sqrt(Fc)) and x = -n / 0.86 (f = -1, F = sqrt(Fc)); and parameter sets in which
+# exactly one Fc term is non-zero and equals 1/2.  A wrong 0.14, 1.27, 0.67, 0.4 or 0.75, or a
+# swapped role of T***, T* or T**, moves F away from these values.
+_LN2 = math.log(2.0)
+_TROE_ISOLATED = {
+    # (a, T***, T*, T**) at T = 1000 K; each gives Fc = 1/2 from a single term
+    "T***": (0.0, 1000.0 / _LN2, 1e30, 1e30),
+    "T*": (1.0, 1e30, 1000.0 / _LN2, 1e30),
+    "T**": (0.0, 1e-30, 1e30, 1000.0 * _LN2),
+}
+
+
+@pytest.mark.parametrize("term", sorted(_TROE_ISOLATED))
+@pytest.mark.parametrize("point", ["centre", "f=+1", "f=-1"])
+def test_troe_broadening_closed_forms(term, point, tmp_path):
+    T, P = 1000.0, 2.0e5
+    A = 1.0e3
+    a7A, a7B = 5.0, 5.7
+    y, Pa = TM.isomer_state(T=T, P=P)
+    base = TM.isomer_mechanism(0, A=A, T=T)
+    rho, C = TM.concentrations(base, y, P)
+    M = C[0] + C[1] + 2.5 * C[2]
+    kinf = A * T / 2.0
+    Fc = 0.5
+    L = math.log10(Fc)
+    c, n = -0.4 - 0.67 * L, 0.75 - 1.27 * L
+    x = {"centre": 0.0, "f=+1": n / 1.14, "f=-1": -n / 0.86}[point]
+    F = Fc if point == "centre" else math.sqrt(Fc)
+    Pr = 10.0 ** (x - c)
+    k0 = Pr * kinf / M
+    mech = TM.isomer_mechanism(3, A=A, T=T, a7A=a7A, a7B=a7B, low=(k0, 0.0, 0.0), troe=_TROE_ISOLATED[term])
+    m = O.Mechanism(TM.write(mech, tmp_path / "troe.ckm"))
+    kf = kinf * Pr / (1.0 + Pr) * F
+    kr = kf / math.exp(a7B - a7A)
+    f = m.rhs(y, Pa)
+    assert f[1, 0] == pytest.approx(-kf * y[1, 0] + kr * y[2, 0], rel=1e-12)
+    assert f[2, 0] == pytest.approx(kf * y[1, 0] - kr * y[2, 0], rel=1e-12)
+
