@@ -185,6 +185,32 @@ int ck_integrate_rkf45(const ck_mech *m, int64_t n, double *y, int64_t ld, const
                        int32_t *status, int32_t *n_accept, int32_t *n_reject, void *stream);
 
 /*
+ * Graph-driven step loop (the persistent-kernel batch of Section 5.2 / Algorithm 2 with the host
+ * out of the per-launch path).  Integrates every reactor from t[r] to t_end[r] with method 0
+ * (ROS4) or 1 (RKF45) as a sequence of bounded launches of the integrator chosen by o (at most
+ * launch_steps attempted steps per reactor each, resuming from (t, h)).  launches_per_graph such
+ * launches, each followed by a small kernel that adds its step counts into n_accept / n_reject and
+ * updates status[], are captured once into a HIP graph together with a device-side count of the
+ * reactors still short of t_end; the graph is replayed on `stream` and the host reads that count
+ * once per replay (one host synchronisation per launches_per_graph launches).  The loop ends when
+ * no reactor is left or when replays * launches_per_graph * launch_steps >= o->max_steps (the
+ * budget is rounded up to whole replays).  A reactor that ends with CK_ST_H_UNDERFLOW or
+ * CK_ST_NONFINITE is frozen for the remaining launches and keeps that status.
+ *   t, h     required [n] in/out (start time and step; zeros start from t = 0 with EstimateH0).
+ *   status, n_accept, n_reject   [n] outputs: totals over every launch.
+ *   replays  optional out: graph replays run.
+ *   workspace  device buffer of ck_graph_workspace_bytes(), or NULL (library-owned, per stream).
+ * Synchronous: returns after the last replay has completed.  Results equal those of the same
+ * launches issued one by one (bitwise for every kernel but CK_KERNEL_GROUP at N > 64).
+ * launch_steps >= 1, 1 <= launches_per_graph <= 64.
+ */
+int ck_integrate_graph(const ck_mech *m, int32_t method, int64_t n, double *y, int64_t ld, const double *p,
+                       const double *t_end, double *t, double *h, const ck_opts *o, int32_t launch_steps,
+                       int32_t launches_per_graph, void *workspace, int32_t *status, int32_t *n_accept,
+                       int32_t *n_reject, int32_t *replays, void *stream);
+size_t ck_graph_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts *o);
+
+/*
  * Variants of ck_rhs_eval / ck_jacobian_eval with an explicit kernel family
  * (CK_KERNEL_LANE: one reactor per lane, coalesced; CK_KERNEL_WAVE: one
  * reactor per wavefront, the family the wavefront integrators use;

@@ -36,7 +36,8 @@ _lib = None
 
 EXPORTS = ["ck_opts_default", "ck_strerror", "ck_mechanism_load", "ck_mechanism_free", "ck_mechanism_info",
            "ck_rhs_eval", "ck_rhs_eval_ex", "ck_jacobian_eval", "ck_jacobian_eval_ex", "ck_workspace_bytes",
-           "ck_integrate_ros4", "ck_integrate_rkf45"]
+           "ck_integrate_ros4", "ck_integrate_rkf45", "ck_integrate_graph",
+           "ck_graph_workspace_bytes"]
 
 
 def lib():
@@ -62,6 +63,10 @@ def lib():
         sig = [vp, i64, dp, i64, dp, dp, dp, dp, C.POINTER(Opts), vp, i32p, i32p, i32p, vp]
         L.ck_integrate_ros4.argtypes = sig
         L.ck_integrate_rkf45.argtypes = sig
+        L.ck_integrate_graph.argtypes = [vp, C.c_int32, i64, dp, i64, dp, dp, dp, dp, C.POINTER(Opts), C.c_int32,
+                                         C.c_int32, vp, i32p, i32p, i32p, C.POINTER(C.c_int32), vp]
+        L.ck_graph_workspace_bytes.argtypes = [vp, i64, C.POINTER(Opts)]
+        L.ck_graph_workspace_bytes.restype = C.c_size_t
         _lib = L
     return _lib
 
@@ -213,3 +218,36 @@ def integrate(mech, y, p, t_end, method="ros4", t=None, h=None, workspace=None, 
     _check(fn(mech.handle, n, _ptr(yy), ld, _ptr(p), _ptr(te), _ptr(t), _ptr(h), C.byref(o), _ptr(workspace),
               _ptr(st), _ptr(na), _ptr(nr), _stream(stream)))
     return dict(y=yy, t=t, h=h, status=st, n_accept=na, n_reject=nr)
+
+
+def integrate_graph(mech, y, p, t_end, method="ros4", launch_steps=500, launches_per_graph=8, t=None, h=None,
+                    workspace=None, stream=None, inplace=False, **opts):
+    """Integrate to t_end with the graph-driven step loop (ck_integrate_graph): bounded launches of
+    `launch_steps` attempted steps, captured `launches_per_graph` at a time in a HIP graph and replayed
+    until no reactor is left (or opts' max_steps is spent).  Synchronous.  Returns dict(y, t, h, status,
+    n_accept, n_reject, replays); t and h are allocated (zeros) when not given."""
+    _state(y, mech.N)
+    n = y.shape[1]
+    dev = y.device
+    yy = y if inplace else y.clone(memory_format=torch.contiguous_format)
+    ld = _state(yy, mech.N)
+    _vec(p, n, dev, "p")
+    t = torch.zeros(n, dtype=torch.float64, device=dev) if t is None else _vec(t, n, dev, "t")
+    h = torch.zeros(n, dtype=torch.float64, device=dev) if h is None else _vec(h, n, dev, "h")
+    te = t_end if torch.is_tensor(t_end) else torch.full((n,), float(t_end), dtype=torch.float64, device=dev)
+    _vec(te, n, dev, "t_end")
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+    na = torch.empty(n, dtype=torch.int32, device=dev)
+    nr = torch.empty(n, dtype=torch.int32, device=dev)
+    o = make_opts(**opts)
+    if workspace is not None:
+        need = int(lib().ck_graph_workspace_bytes(mech.handle, n, C.byref(o)))
+        if not torch.is_tensor(workspace) or workspace.device != dev or not workspace.is_contiguous() or \
+                workspace.numel() * workspace.element_size() < need:
+            raise CkError(f"workspace must be a contiguous tensor on {dev} of at least {need} bytes")
+    reps = C.c_int32(0)
+    _check(lib().ck_integrate_graph(mech.handle, {"ros4": 0, "rkf45": 1}[method], n, _ptr(yy), ld, _ptr(p),
+                                    _ptr(te), _ptr(t), _ptr(h), C.byref(o), int(launch_steps),
+                                    int(launches_per_graph), _ptr(workspace), _ptr(st), _ptr(na), _ptr(nr),
+                                    C.byref(reps), _stream(stream)))
+    return dict(y=yy, t=t, h=h, status=st, n_accept=na, n_reject=nr, replays=reps.value)

@@ -258,3 +258,159 @@ extern "C" int ck_integrate_rkf45(const ck_mech *m, int64_t n, double *y, int64_
                                   int32_t *status, int32_t *n_accept, int32_t *n_reject, void *stream) {
     return integrate(1, m, n, y, ld, p, t_end, t, h, o, workspace, status, n_accept, n_reject, stream);
 }
+
+// ---------------------------------------------------------------------------------------
+// Graph-driven step loop: bounded launches captured K at a time in a HIP graph
+// ---------------------------------------------------------------------------------------
+namespace {
+
+// Bookkeeping of the graph loop, after the integrator's own workspace (256-byte aligned pieces).
+struct GraphWs {
+    size_t kernel_bytes, te, st, acc, rej, remaining, total;
+    GraphWs(size_t kbytes, int64_t n) {
+        auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+        const size_t nn = size_t(std::max<int64_t>(n, 1));
+        kernel_bytes = up(kbytes);
+        te = kernel_bytes;
+        st = te + up(nn * sizeof(double));
+        acc = st + up(nn * sizeof(int32_t));
+        rej = acc + up(nn * sizeof(int32_t));
+        remaining = rej + up(nn * sizeof(int32_t));
+        total = remaining + 256;
+    }
+};
+
+__global__ void graph_init_kernel(int64_t n, const double *t_end, double *te, int32_t *status, int32_t *nacc,
+                                  int32_t *nrej) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    te[i] = t_end[i];
+    status[i] = CK_ST_OK;
+    nacc[i] = 0;
+    nrej[i] = 0;
+}
+
+__global__ void graph_zero_kernel(unsigned *c) { *c = 0u; }
+
+// Folds one bounded launch into the totals.  A reactor that ended with H_UNDERFLOW or NONFINITE is
+// frozen: its working end time becomes its current time, so later launches leave it unchanged, and
+// its status is kept.  With `count`, reactors still short of t_end (MAX_STEPS) are counted.
+__global__ void graph_merge_kernel(int64_t n, const double *t, double *te, const int32_t *st_k, const int32_t *acc_k,
+                                   const int32_t *rej_k, int32_t *status, int32_t *nacc, int32_t *nrej,
+                                   unsigned *remaining, int count) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool open = false;
+    if (i < n) {
+        nacc[i] += acc_k[i];
+        nrej[i] += rej_k[i];
+        const int prev = status[i];
+        if (prev != CK_ST_H_UNDERFLOW && prev != CK_ST_NONFINITE) {
+            const int sk = st_k[i];
+            status[i] = sk;
+            if (sk == CK_ST_H_UNDERFLOW || sk == CK_ST_NONFINITE) te[i] = t[i];
+            open = sk == CK_ST_MAX_STEPS;
+        }
+    }
+    if (count) {
+        const unsigned long long b = __ballot(open);
+        if (b && __lane_id() == __ffsll((long long)b) - 1) atomicAdd(remaining, unsigned(__popcll(b)));
+    }
+}
+
+struct StreamHolder {
+    hipStream_t s = nullptr;
+    ~StreamHolder() {
+        if (s) hipStreamDestroy(s);
+    }
+};
+struct GraphHolder {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    ~GraphHolder() {
+        if (e) hipGraphExecDestroy(e);
+        if (g) hipGraphDestroy(g);
+    }
+};
+
+}  // namespace
+
+extern "C" size_t ck_graph_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts *o) {
+    const size_t k = ck_workspace_bytes(m, n, o);
+    if (k == 0) return 0;
+    return GraphWs(k, n).total;
+}
+
+extern "C" int ck_integrate_graph(const ck_mech *mc, int32_t method, int64_t n, double *y, int64_t ld,
+                                  const double *p, const double *t_end, double *t, double *h, const ck_opts *o,
+                                  int32_t launch_steps, int32_t launches_per_graph, void *workspace,
+                                  int32_t *status, int32_t *n_accept, int32_t *n_reject, int32_t *replays,
+                                  void *stream) {
+    ck_mech *m = const_cast<ck_mech *>(mc);
+    if (method != 0 && method != 1) return CK_EINVAL;
+    if (!check_state_args(m, n, y, ld, p, y)) return CK_EINVAL;
+    IntOpts io;
+    int rc = validate_opts(o, io);
+    if (rc != CK_OK) return rc;
+    if (launch_steps < 1 || launches_per_graph < 1 || launches_per_graph > 64) return CK_EINVAL;
+    if (replays) *replays = 0;
+    if (n == 0) return CK_OK;
+    if (!t_end || !t || !h || !status || !n_accept || !n_reject) return CK_EINVAL;
+    rc = choose_kernel(m, method, o);
+    if (rc < 0) return rc;
+    ck_opts d;
+    ck_opts_default(&d);
+    ck_opts lo = o ? *o : d;                 // per-launch options: a bounded attempted-step budget
+    const int64_t budget = lo.max_steps;
+    lo.max_steps = launch_steps;
+    DeviceGuard g(m->device);
+    if (!g.ok) return CK_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const GraphWs L(ck_workspace_bytes(m, n, &lo), n);
+    if (L.kernel_bytes == 0) return CK_EHIP;
+    char *ws = static_cast<char *>(workspace);
+    if (!ws) {
+        void *v = nullptr;
+        rc = cached_ws(m, s, L.total, &v);
+        if (rc != CK_OK) return rc;
+        ws = static_cast<char *>(v);
+    }
+    double *te = reinterpret_cast<double *>(ws + L.te);
+    int32_t *st_k = reinterpret_cast<int32_t *>(ws + L.st);
+    int32_t *acc_k = reinterpret_cast<int32_t *>(ws + L.acc);
+    int32_t *rej_k = reinterpret_cast<int32_t *>(ws + L.rej);
+    unsigned *rem = reinterpret_cast<unsigned *>(ws + L.remaining);
+    const dim3 blk(256), grd(unsigned((n + 255) / 256));
+
+    // capture K launches (+ bookkeeping) on a private stream; the graph is replayed on `s`
+    StreamHolder cs;
+    CK_HIP_TRY(hipStreamCreateWithFlags(&cs.s, hipStreamNonBlocking));
+    GraphHolder gh;
+    CK_HIP_TRY(hipStreamBeginCapture(cs.s, hipStreamCaptureModeRelaxed));
+    int crc = CK_OK;
+    for (int k = 0; k < launches_per_graph && crc == CK_OK; k++) {
+        crc = integrate(method, m, n, y, ld, p, te, t, h, &lo, ws, st_k, acc_k, rej_k, cs.s);
+        if (crc != CK_OK) break;
+        const bool last = k == launches_per_graph - 1;
+        if (last) graph_zero_kernel<<<1, 1, 0, cs.s>>>(rem);
+        graph_merge_kernel<<<grd, blk, 0, cs.s>>>(n, t, te, st_k, acc_k, rej_k, status, n_accept, n_reject, rem,
+                                                   last ? 1 : 0);
+    }
+    const hipError_t ec = hipStreamEndCapture(cs.s, &gh.g);
+    if (crc != CK_OK) return crc;
+    if (ec != hipSuccess || hipGetLastError() != hipSuccess) return CK_EHIP;
+    CK_HIP_TRY(hipGraphInstantiate(&gh.e, gh.g, nullptr, nullptr, 0));
+
+    graph_init_kernel<<<grd, blk, 0, s>>>(n, t_end, te, status, n_accept, n_reject);
+    CK_HIP_TRY(hipGetLastError());
+    int32_t done = 0;
+    for (;;) {
+        CK_HIP_TRY(hipGraphLaunch(gh.e, s));
+        done++;
+        unsigned left = 0;
+        CK_HIP_TRY(hipMemcpyAsync(&left, rem, sizeof(left), hipMemcpyDeviceToHost, s));
+        CK_HIP_TRY(hipStreamSynchronize(s));
+        if (left == 0 || int64_t(done) * launches_per_graph * launch_steps >= budget) break;
+    }
+    if (replays) *replays = done;
+    return CK_OK;
+}
