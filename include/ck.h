@@ -214,12 +214,15 @@ size_t ck_graph_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts *o);
  * Variants of ck_rhs_eval / ck_jacobian_eval with an explicit kernel family
  * (CK_KERNEL_LANE: one reactor per lane, coalesced; CK_KERNEL_WAVE: one
  * reactor per wavefront, the family the wavefront integrators use;
- * CK_KERNEL_AUTO: the library's choice).  ck_rhs_eval uses CK_KERNEL_AUTO
- * (wavefront); ck_jacobian_eval uses CK_KERNEL_LANE.  CK_KERNEL_WAVE
- * Jacobians need N <= 64 (CK_EUNSUPPORTED otherwise).  The lane family uses
- * a library-owned scratch buffer sized for n.  reactor: CK_REACTOR_CONST_P (p =
- * pressures) or CK_REACTOR_CONST_V (p = densities; wavefront family only,
- * CK_EUNSUPPORTED with CK_KERNEL_LANE).
+ * CK_KERNEL_AUTO: the library's choice).  ck_rhs_eval and ck_jacobian_eval
+ * use CK_KERNEL_AUTO, which is the deep-vectorised family (Section 4) for
+ * N <= 128.  A CK_KERNEL_WAVE Jacobian runs one reactor per wavefront for
+ * N <= 64 and one reactor per four-wavefront workgroup (matrix rows split
+ * over thread pairs, as in the N > 64 integrator) for 64 < N <= 128
+ * (constant pressure only there; CK_EUNSUPPORTED otherwise).  The lane family
+ * uses a library-owned scratch buffer sized for n.  reactor:
+ * CK_REACTOR_CONST_P (p = pressures) or CK_REACTOR_CONST_V (p = densities;
+ * wavefront family only, N <= 64, CK_EUNSUPPORTED with CK_KERNEL_LANE).
  */
 int ck_rhs_eval_ex(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p, double *dydt,
                    int32_t kernel, int32_t reactor, void *stream);

@@ -25,7 +25,7 @@ struct DeviceGuard {
 
 // Library-owned workspace of a mechanism for calls on `s` that pass none.  Each stream gets its
 // own buffer: two streams running the persistent kernels at once must not share a queue counter.
-// Growing a buffer waits for the device before freeing the old one.
+// Growing a buffer waits for that stream (the only one that uses it) before freeing the old one.
 int cached_ws(ck_mech *m, hipStream_t s, size_t bytes, void **out) {
     std::lock_guard<std::mutex> lk(m->ws_mutex);
     ck_mech::StreamWs *e = nullptr;
@@ -37,7 +37,7 @@ int cached_ws(ck_mech *m, hipStream_t s, size_t bytes, void **out) {
     }
     if (e->bytes < bytes) {
         if (e->ptr) {
-            hipDeviceSynchronize();
+            if (hipStreamSynchronize(s) != hipSuccess) return CK_EHIP;
             hipFree(e->ptr);
             e->ptr = nullptr;
             e->bytes = 0;
@@ -213,6 +213,9 @@ extern "C" int ck_jacobian_eval_ex(const ck_mech *mc, int64_t n, const double *y
         if (kernel == CK_KERNEL_LANE) return CK_EUNSUPPORTED;
         kernel = CK_KERNEL_WAVE;
     }
+    // default: the deep-vectorised family (one reactor per wavefront, or per four-wavefront group
+    // for 64 < N <= 128); the lane kernel beyond that
+    if (kernel == CK_KERNEL_AUTO) kernel = m->dev.N <= 128 ? CK_KERNEL_WAVE : CK_KERNEL_LANE;
     if (n == 0) return CK_OK;
     DeviceGuard g(m->device);
     if (!g.ok) return CK_EHIP;
@@ -226,7 +229,7 @@ extern "C" int ck_jacobian_eval_ex(const ck_mech *mc, int64_t n, const double *y
 
 extern "C" int ck_jacobian_eval(const ck_mech *m, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
                                 void *stream) {
-    return ck_jacobian_eval_ex(m, n, y, ld, p, jac, CK_KERNEL_LANE, CK_REACTOR_CONST_P, stream);
+    return ck_jacobian_eval_ex(m, n, y, ld, p, jac, CK_KERNEL_AUTO, CK_REACTOR_CONST_P, stream);
 }
 
 extern "C" size_t ck_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts *o) {

@@ -791,6 +791,35 @@ __global__ void __launch_bounds__(64 * W) coop_kernel(DevMech M, int64_t n, doub
     }
 }
 
+// Standalone analytic Jacobian for N > 64 (deep vectorisation: one reactor per four-wavefront
+// group, the half-row assembly of the integrator with dg = 0, so a = -J exactly).  Rates are
+// evaluated again in the second column window (no park slice).  jac[(i N + j) ld + r] = dfi/dyj.
+template <int NP>
+__global__ void __launch_bounds__(256) jac_group_kernel(DevMech M, int64_t n, const double *y, int64_t ld,
+                                                        const double *p, double *jac) {
+    constexpr int H = NP / 2;
+    extern __shared__ double lds_raw[];
+    Lds L = carve(lds_raw, M.nsp, H, true);
+    init_lds(M, L, int(threadIdx.x), 256);
+    const int N = M.N, tid = int(threadIdx.x);
+    const int row = tid >> 1, half = tid & 1;
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const double yv = tid < N ? y[int64_t(tid) * ld + r] : 0.0;
+        double a[H];
+        double f;
+        iteration_rows_half<NP>(M, L, yv, p[r], 0.0, a, f);
+        if (row < N) {
+            double *out = jac + int64_t(row) * N * ld + r;
+#pragma unroll
+            for (int j = 0; j < H; j++) {
+                const int c = half * H + j;
+                if (c < N) out[int64_t(c) * ld] = -a[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void zero_queue_kernel(unsigned *q) { *q = 0u; }
 
 // Workgroups per CU of a parking kernel are capped so that the parked rows fit the workspace.
@@ -841,6 +870,37 @@ int launch_half(const DevMech &M, int64_t n, double *y, int64_t ld, const double
 }  // namespace coop
 
 bool coop_supported(const DevMech &M) { return M.N <= 128; }
+
+namespace coop {
+template <int NP>
+int launch_jac_group(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
+                     hipStream_t s) {
+    const size_t lds = lds_doubles(M.nsp, NP / 2, true) * sizeof(double);
+    auto kern = jac_group_kernel<NP>;
+    if (lds > 64 * 1024 && hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+        return CK_EHIP;
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CK_EHIP;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return CK_EHIP;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 256, lds) != hipSuccess || per < 1) return CK_EHIP;
+    int64_t grid = int64_t(cus) * per;
+    if (grid > n) grid = n;
+    kern<<<dim3(unsigned(grid)), dim3(256), lds, s>>>(M, n, y, ld, p, jac);
+    return hipGetLastError() == hipSuccess ? CK_OK : CK_EHIP;
+}
+}  // namespace coop
+
+int launch_jac_coop(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
+                    hipStream_t s) {
+    switch (((M.N + 7) / 8) * 8) {
+#define CK_JG(NPV) \
+    case NPV: return coop::launch_jac_group<NPV>(M, n, y, ld, p, jac, s);
+        CK_JG(72) CK_JG(80) CK_JG(88) CK_JG(96) CK_JG(104) CK_JG(112) CK_JG(120) CK_JG(128)
+#undef CK_JG
+        default: return CK_EUNSUPPORTED;
+    }
+}
 
 size_t coop_ws_bytes(const DevMech &M, int cus) {
     if (M.N <= 64) return 256;

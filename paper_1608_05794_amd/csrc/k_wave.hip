@@ -1171,7 +1171,7 @@ int launch_rhs_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, co
 
 int launch_jac_wave(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
                     int cv, hipStream_t s) {
-    if (M.N > 64) return CK_EUNSUPPORTED;
+    if (M.N > 64) return cv ? CK_EUNSUPPORTED : launch_jac_coop(M, n, y, ld, p, jac, s);
     const size_t lds = lds_doubles(M.nsp, true) * sizeof(double);
     const unsigned grid = unsigned((n + 7) / 8 * 8);
     jac_wave_kernel<<<dim3(grid), dim3(64), lds, s>>>(M, n, y, ld, p, jac, cv);
