@@ -136,6 +136,8 @@ def parse():
                          "forms; methods: small configuration with both integrators, transfers, analytic vs "
                          "forward-difference Jacobian; peaks: achievable GEMM, FMA and copy rates (one "
                          "JSON line each, bounded workloads)")
+    ap.add_argument("--batching-reactors", type=int, default=32768, help="batching suite: reactors (first of the batch)")
+    ap.add_argument("--batching-t-end", type=float, default=1e-13, help="batching suite: common end time (s)")
     ap.add_argument("--serve-requests", type=int, default=32, help="serving suite: arrivals served")
     ap.add_argument("--serve-t-scale", type=float, default=1e-3, help="serving suite: factor on drawn end times")
     ap.add_argument("--serve-time-limit", type=float, default=150.0, help="serving suite: wall time limit (s)")
@@ -209,39 +211,109 @@ def _timed_integrate(ck, torch, g, y, P, t_end, **opts):
     return r, e0.elapsed_time(e1) / 1e3
 
 
+def _bounded_loop(ck, torch, g, y, P, t_end, launch_steps, log=None, **opts):
+    """Integrate a copy of y to t_end in bounded launches resuming from (t, h), host-synchronised per
+    launch (the host reads the statuses to decide whether to launch again).  Returns (result with
+    summed step counts, seconds from the first launch to the last status read, launches)."""
+    n = y.shape[1]
+    yy = y.clone()
+    t = torch.zeros(n, dtype=torch.float64, device=y.device)
+    h = torch.zeros_like(t)
+    steps = torch.zeros(n, dtype=torch.int64, device=y.device)
+    ws = torch.empty(g.workspace_bytes(n, **opts), dtype=torch.uint8, device=y.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    launches = 0
+    while True:
+        r = ck.integrate(g, yy, P, t_end, t=t, h=h, workspace=ws, inplace=True, max_steps=launch_steps, **opts)
+        steps += r["n_accept"] + r["n_reject"]
+        launches += 1
+        left = int((r["status"] == 1).sum().item())
+        if log:
+            log(f"  launch {launches}: {time.perf_counter() - t0:.1f} s, {left} reactors unfinished")
+        if left == 0:
+            break
+    torch.cuda.synchronize()
+    r["steps"] = steps
+    return r, time.perf_counter() - t0, launches
+
+
 def suite_batching(a):
-    """Batching against divergence (111 species, 262144 reactors, half near ignition and half cold):
-    the persistent work-queue workgroup kernel against the plain one-reactor-per-lane kernel, each
-    given the same number of attempted steps per reactor; and the waste the lane kernel would incur,
-    from the step counts of a sample integrated to completion."""
+    """Batching against divergence (Section 4, Algorithm 2; Section 5.2, Eq. waste) on the 111-species
+    half-hot / half-cold states: every reactor integrated to a common end time, so adaptive step counts
+    diverge.  Timed: the persistent work-queue workgroup kernel in bounded launches driven from the
+    host and replayed from a HIP graph (ck_integrate_graph), against the one-reactor-per-lane kernel
+    (lockstep 64-lane wavefronts), whose waste is measured from its own step counts; the lane kernel
+    again with the reactors ordered by initial temperature (a stiffness proxy), which groups similar
+    step counts into a wavefront.  Bounded so the lane kernel finishes in about a minute: the first
+    --batching-reactors states of the 262144-reactor batch to --batching-t-end.  Also the launch
+    configuration chosen by the autotuner and the Eq. waste CDFs of a sample integrated further."""
     import torch
 
-    from paper_1608_05794_amd import ck, metrics, synth
-    out = {"suite": "batching", "unit": "reactor-steps/s", "data": "synthetic", "dtype": "f64"}
-    for mech, n, steps, kernels in (("M111", 262144, 24, ("group", "lane")), ("M53", 131072, 60, ("wave", "lane"))):
-        g = ck.Mechanism(synth.mechanism_file(mech))
-        y, P = _states(synth, torch, mech, n, {"M53": 1002, "M111": 1003}[mech])
-        row = {}
-        for k in kernels:
-            r, dt = _timed_integrate(ck, torch, g, y, P, 1e-3, kernel=k, max_steps=steps)
-            done = float((r["n_accept"] + r["n_reject"]).sum().item())
-            row[k] = {"reactor_steps_per_s": done / dt, "seconds": dt}
-            print(f"batching {mech} {k}: {done / dt / 1e6:.3f} M reactor-steps/s", file=sys.stderr, flush=True)
-        row["speedup"] = row[kernels[0]]["reactor_steps_per_s"] / row[kernels[1]]["reactor_steps_per_s"]
-        out[f"{mech}_x{n}_{steps}_steps"] = row
+    from paper_1608_05794_amd import ck, metrics, synth, tune
+    n, te = a.batching_reactors, a.batching_t_end
+    out = {"suite": "batching", "data": "synthetic", "dtype": "f64",
+           "workload": f"M111 (111 species, 784 reactions), first {n} of the 262144 half-hot / half-cold states "
+                       f"(seed 1003), ROS4 to a common t_end = {te:g} s, rtol 1e-8, atol 1e-12"}
+    g = ck.Mechanism(synth.mechanism_file("M111"))
+    y0, P0 = synth.reactor_states(111, 262144, "divergent", seed=1003)
+    y = torch.as_tensor(np.ascontiguousarray(y0[:, :n]), device="cuda")
+    P = torch.as_tensor(np.ascontiguousarray(P0[:n]), device="cuda")
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+
+    def row(r, dt, **kw):
+        s = r["steps"] if "steps" in r else r["n_accept"] + r["n_reject"]
+        s = s.to(torch.float64)
+        st = torch.bincount(r["status"].to(torch.int64), minlength=4).tolist()
+        return dict(seconds=dt, reactors_per_s=n / dt, reactor_steps_per_s=float(s.sum().item()) / dt,
+                    mean_steps=float(s.mean().item()), max_steps=float(s.max().item()), status_histogram=st, **kw)
+
+    # persistent workgroup kernel: host loop of bounded launches, then the graph-driven loop
+    _bounded_loop(ck, torch, g, y[:, :256], P[:256], te, 200, kernel="group")          # warm-up
+    r, dt, nl = _bounded_loop(ck, torch, g, y, P, te, 200, log=log, kernel="group")
+    out["persistent_host_loop"] = row(r, dt, launches=nl, launch_steps=200)
+    ref = r
+    log(f"batching persistent host loop: {dt:.2f} s, {nl} launches")
+    gws = torch.empty(g.graph_workspace_bytes(n, kernel="group"), dtype=torch.uint8, device="cuda")
+    ck.integrate_graph(g, y[:, :256], P[:256], te, launch_steps=200, launches_per_graph=4, kernel="group",
+                       workspace=gws)                                                # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gr = ck.integrate_graph(g, y, P, te, launch_steps=200, launches_per_graph=4, kernel="group", workspace=gws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gr["steps"] = gr["n_accept"] + gr["n_reject"]
+    out["persistent_graph_loop"] = row(gr, dt, replays=gr["replays"], launches_per_graph=4, launch_steps=200)
+    out["persistent_graph_loop"]["statuses_equal_host_loop"] = bool(torch.equal(gr["status"], ref["status"]))
+    log(f"batching persistent graph loop: {dt:.2f} s, {gr['replays']} replays")
+
+    # one reactor per lane (lockstep 64-lane wavefronts), in bounded launches of 100 attempted steps
+    # resuming from (t, h); the lockstep waste from its own step counts
+    for tag, order in (("lane", None), ("lane_sorted_by_T0", torch.argsort(y[0]))):
+        yy, pp = (y, P) if order is None else (y[:, order].contiguous(), P[order].contiguous())
+        _timed_integrate(ck, torch, g, yy, pp, te, kernel="lane", max_steps=1)     # scratch allocation, code load
+        r, dt, nl = _bounded_loop(ck, torch, g, yy, pp, te, 100, log=log, kernel="lane")
+        s = r["steps"].cpu().numpy()
+        w = metrics.waste(s, 64)
+        out[tag] = row(r, dt, launches=nl, launch_steps=100, mean_waste_64=float(w.mean()),
+                       lane_efficiency_64=metrics.lane_efficiency(s, 64),
+                       waste_cdf_64={str(k): v for k, v in metrics.waste_cdf(s, widths=(64,))[64].items()})
+        log(f"batching {tag}: {dt:.2f} s, mean waste {w.mean():.3f}")
+    out["speedup_persistent_over_lane"] = out["persistent_host_loop"]["reactors_per_s"] / out["lane"]["reactors_per_s"]
+    out["speedup_graph_over_host_loop"] = (out["persistent_graph_loop"]["reactors_per_s"] /
+                                           out["persistent_host_loop"]["reactors_per_s"])
+
     # launch configuration chosen by the autotuner on a 16384-reactor sample of each workload
-    from paper_1608_05794_amd import tune
     for mech, seed in (("M53", 1002), ("M111", 1003)):
-        g = ck.Mechanism(synth.mechanism_file(mech))
-        y, P = _states(synth, torch, mech, 16384, seed)
-        best, table = tune.tune(g, y, P, 1e-3, steps=12)
+        gm = ck.Mechanism(synth.mechanism_file(mech))
+        ys, Ps = _states(synth, torch, mech, 16384, seed)
+        best, table = tune.tune(gm, ys, Ps, 1e-3, steps=12)
         out[f"autotune_{mech}"] = {"best": {k: best[k] for k in ("kernel", "blocks_per_cu")},
                                    "table": [[c["kernel"], c["blocks_per_cu"], v] for c, v in table]}
-        print(f"autotune {mech}: {best}", file=sys.stderr, flush=True)
-    # waste of lockstep groups (Eq. waste) from complete integrations of a 111-species sample
-    g = ck.Mechanism(synth.mechanism_file("M111"))
-    y, P = _states(synth, torch, "M111", 2048, 1003)
-    r, dt = _timed_integrate(ck, torch, g, y, P, 1e-9, kernel="group")
+        log(f"autotune {mech}: {best}")
+    # Eq. waste CDFs for widths 4..64 from a sample integrated further (to 1e-9 s)
+    ys, Ps = _states(synth, torch, "M111", 2048, 1003)
+    r, dt = _timed_integrate(ck, torch, g, ys, Ps, 1e-9, kernel="group")
     st = (r["n_accept"] + r["n_reject"]).cpu().numpy()
     out["waste_sample"] = {
         "reactors": 2048, "t_end": 1e-9, "mean_steps": float(st.mean()), "max_steps": int(st.max()),

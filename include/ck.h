@@ -59,13 +59,18 @@ enum {
     CK_KERNEL_AUTO = 0,    /* ROS4: WAVE if N <= 64, else GROUP if N <= 128; RKF45: WAVE if N <= 128 */
     CK_KERNEL_LANE = 1,    /* one reactor per lane, all scratch in global memory (Algorithm 2 analogue) */
     CK_KERNEL_WAVE = 2,    /* one reactor per 64-lane wavefront, persistent work queue, LU in registers */
-    CK_KERNEL_GROUP = 3    /* ROS4 only: one reactor per workgroup of 1 (N <= 64) or 4 (N <= 128, matrix
+    CK_KERNEL_GROUP = 3,   /* ROS4 only: one reactor per workgroup of 1 (N <= 64) or 4 (N <= 128, matrix
                               rows split over thread pairs) wavefronts, persistent work queue,
                               Gauss-Jordan inverse in registers.  With 4 wavefronts the reaction
                               contributions are summed with LDS atomics in an order that varies
                               between runs: results agree to rounding, not bit for bit.  Every other
                               kernel gives bitwise identical results for identical inputs, whatever
                               the batch a reactor is in */
+    CK_KERNEL_GROUP_TILE = 4 /* ROS4 only, 64 < N <= 128: the four-wavefront workgroup with the
+                              iteration matrix in 16x16 tiles and a blocked Gauss-Jordan inverse
+                              (panels of 16 columns, partial pivoting) whose rank-16 updates run on
+                              the FP64 matrix cores (MFMA).  Same pivots and results as GROUP up to
+                              rounding; the same summation caveat applies */
 };
 
 /* Reactor form (Section 3).  Constant pressure: p[] holds pressures (Pa); the density follows

@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libck.so")
 
-KERNELS = {"auto": 0, "lane": 1, "wave": 2, "group": 3}
+KERNELS = {"auto": 0, "lane": 1, "wave": 2, "group": 3, "tile": 4}
 PRECISIONS = {"fp64": 0, "fp32_refine": 1}
 JACOBIANS = {"analytic": 0, "fd": 1}
 REACTORS = {"cp": 0, "cv": 1}   # constant pressure (p = pressures, Pa) / constant volume (p = densities, kg/m^3)
@@ -149,6 +149,10 @@ class Mechanism:
     def workspace_bytes(self, n, **opts):
         o = make_opts(**opts)
         return int(lib().ck_workspace_bytes(self._h, int(n), C.byref(o)))
+
+    def graph_workspace_bytes(self, n, **opts):
+        o = make_opts(**opts)
+        return int(lib().ck_graph_workspace_bytes(self._h, int(n), C.byref(o)))
 
 
 def rhs(mech, y, p, out=None, kernel=None, stream=None, reactor="cp"):

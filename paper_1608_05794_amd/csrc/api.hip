@@ -64,7 +64,7 @@ int validate_opts(const ck_opts *o, IntOpts &io) {
     if (!(o->h_fixed >= 0.0) || !(o->h0 >= 0.0)) return CK_EINVAL;
     if (o->h_fixed == 0.0 && !(o->rtol > 0.0)) return CK_EINVAL;
     if (!(o->atol >= 0.0) || o->max_steps < 1) return CK_EINVAL;
-    if (o->kernel < CK_KERNEL_AUTO || o->kernel > CK_KERNEL_GROUP) return CK_EINVAL;
+    if (o->kernel < CK_KERNEL_AUTO || o->kernel > CK_KERNEL_GROUP_TILE) return CK_EINVAL;
     if (o->precision != CK_PREC_FP64 && o->precision != CK_PREC_FP32_REFINE) return CK_EINVAL;
     if (o->refine_sweeps < 0 || o->refine_sweeps > 3) return CK_EINVAL;
     if (o->blocks_per_cu < 0) return CK_EINVAL;
@@ -102,9 +102,11 @@ int choose_kernel(const ck_mech *m, int method, const ck_opts *o) {
         return CK_KERNEL_WAVE;
     }
     const bool group_ok = method == 0 && fp64 && coop_supported(m->dev);
+    const bool tile_ok = method == 0 && fp64 && tile_supported(m->dev);
     switch (o->kernel) {
         case CK_KERNEL_WAVE: return wave_ok ? CK_KERNEL_WAVE : CK_EUNSUPPORTED;
         case CK_KERNEL_GROUP: return group_ok ? CK_KERNEL_GROUP : CK_EUNSUPPORTED;
+        case CK_KERNEL_GROUP_TILE: return tile_ok ? CK_KERNEL_GROUP_TILE : CK_EUNSUPPORTED;
         case CK_KERNEL_LANE: return fp64 ? CK_KERNEL_LANE : CK_EUNSUPPORTED;
         default:
             if (wave_ok) return CK_KERNEL_WAVE;
@@ -143,6 +145,8 @@ int integrate(int method, const ck_mech *mc, int64_t n, double *y, int64_t ld, c
         return launch_integrate_wave(method, m->dev, n, y, ld, p, t_end, t, h, io, ws, status, nacc, nrej, s);
     if (kern == CK_KERNEL_GROUP)
         return launch_integrate_coop(m->dev, n, y, ld, p, t_end, t, h, io, ws, status, nacc, nrej, s);
+    if (kern == CK_KERNEL_GROUP_TILE)
+        return launch_integrate_tile(m->dev, n, y, ld, p, t_end, t, h, io, ws, status, nacc, nrej, s);
     const int64_t S = round_up(n, 64);
     return launch_integrate_lane(method, m->dev, n, y, ld, p, t_end, t, h, io, static_cast<double *>(ws), S, status,
                                  nacc, nrej, s);
@@ -239,7 +243,7 @@ extern "C" size_t ck_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts 
         const int k = choose_kernel(m, method, o);
         size_t b = 256;
         if (k == CK_KERNEL_LANE) b = lane_bytes(m, n, method);
-        else if (k == CK_KERNEL_WAVE || k == CK_KERNEL_GROUP) {
+        else if (k == CK_KERNEL_WAVE || k == CK_KERNEL_GROUP || k == CK_KERNEL_GROUP_TILE) {
             int cus = 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess)
                 return 0;

@@ -51,12 +51,18 @@ struct Lds {
 };
 
 __host__ __device__ inline int ldj_of(int win) { return win | 1; }
-__host__ __device__ inline size_t lds_doubles(int ns, int win, bool half = false) {
-    return size_t(ns + 1) + 3 * size_t(ns) + 128 + 128 + 16 + 2 * 128 + 128 + 128 + size_t(ns) * ldj_of(win) + 128 +
+// JC region: the staged d wdot/dC window, or at least jc_min doubles (the tile kernel reuses the
+// region as scratch of its blocked elimination)
+__host__ __device__ inline size_t jc_doubles(int ns, int win, size_t jc_min) {
+    const size_t j = size_t(ns) * ldj_of(win) + 128;
+    return j > jc_min ? j : jc_min;
+}
+__host__ __device__ inline size_t lds_doubles(int ns, int win, bool half = false, size_t jc_min = 0) {
+    return size_t(ns + 1) + 3 * size_t(ns) + 128 + 128 + 16 + 2 * 128 + 128 + 128 + jc_doubles(ns, win, jc_min) +
            2 * size_t(ns) + size_t(ns) + 128 + (half ? 4 * 128 + 64 : 0);
 }
 
-__device__ __forceinline__ Lds carve(double *b, int ns, int win, bool half = false) {
+__device__ __forceinline__ Lds carve(double *b, int ns, int win, bool half = false, size_t jc_min = 0) {
     Lds L;
     L.ldj = ldj_of(win);
     L.C = b; b += ns + 1;
@@ -69,7 +75,7 @@ __device__ __forceinline__ Lds carve(double *b, int ns, int win, bool half = fal
     L.PB = b; b += 2 * 128;
     L.BS = b; b += 128;
     L.XS = b; b += 128;
-    L.JC = b; b += size_t(ns) * L.ldj + 128;
+    L.JC = b; b += jc_doubles(ns, win, jc_min);
     L.TB = b; b += ns;
     L.DWT = b; b += ns;
     L.TROW = b; b += ns + 128;
@@ -443,6 +449,7 @@ struct Ros4Coop {
     static constexpr double qinv = 0.25;
     static constexpr size_t kRows = size_t(NP) * 64 * W;   // parked doubles per workgroup
     static constexpr bool kHalf = false;
+    static constexpr size_t kJcMin = 0;
     // the inverse rows go to the workspace while the stage source terms are evaluated and come
     // back as one batch of independent loads before the next products
     __device__ static __forceinline__ void park(const Lds &L, const double (&a)[NP]) {
@@ -655,6 +662,7 @@ struct Ros4CoopHalf {
     static constexpr int H = NP / 2;
     static constexpr bool kHalf = true;
     static constexpr size_t kRows = size_t(H) * 256;   // park-slice doubles per workgroup
+    static constexpr size_t kJcMin = 0;
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h,
                                                 double &ynew, double &e) {
         double a[H];
@@ -671,6 +679,400 @@ struct Ros4CoopHalf {
         const double u3 = gj_apply_half<NP>(a, L, ord, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
         const double u4 =
             gj_apply_half<NP>(a, L, ord, ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
+        ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
+        e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
+        return ok;
+    }
+};
+
+// ---------------------------------------------------------------------------------------
+// Tile variant (N > 64): the iteration matrix lives in 16 x 16 tiles in the accumulator layout of
+// the FP64 16x16x4 matrix-core instruction (lane l, register v of tile (I, J) holds entry
+// (16 I + l / 16 + 4 v, 16 J + l % 16)); wavefront w owns tile rows w and w + 4.  The inverse
+// comes from a blocked Gauss-Jordan elimination in panels of 16 columns: wavefront 0 eliminates
+// the panel (all NP rows; partial pivoting over the rows not yet used as pivots), then every
+// wavefront applies it to its tiles with matrix-core rank-16 updates
+//     A[:, J] <- A[:, J] with the panel's pivot rows zeroed + T * U[:, J],
+// T the eliminated panel (NP x 16) and U the panel's pivot rows before the update (16 x NP), both
+// passed through LDS.  This is the arithmetic of 16 scalar Gauss-Jordan steps regrouped (sums of
+// products in another order), so the result is the same inverse with the same pivots up to
+// rounding; the pivot order of each row is kept for the solves, as in the other forms.
+// ---------------------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Matrix row held in register v of lane group g (= lane / 16) of tile row I.  The FP64 16x16x4
+// instruction interleaves the rows of its accumulator over the lane groups (row g + 4 v of the
+// tile; measured on the device), where the FP32 one keeps them contiguous (4 g + v).
+__device__ __forceinline__ int tile_row(int I, int g, int v) { return 16 * I + g + 4 * v; }
+
+template <int NP>
+struct TileGeom {
+    static_assert(NP % 16 == 0 && NP <= 128, "tile form: NP a multiple of 16, at most 128");
+    static constexpr int TR = NP / 16;            // tile rows (and tile columns)
+    static constexpr int RW = (TR + 3) / 4;       // tile rows per wavefront
+    static constexpr int PLD = NP + 4;            // column stride of an LDS panel buffer (doubles)
+    static constexpr int UBLD = NP;               // row stride of the pivot-row buffer
+    // scratch carved from the JC region: panel buffers [2][16][PLD], pivot rows [16][UBLD], the
+    // pivot row and the pivot column of one elimination step [16 + 128]
+    static constexpr size_t kScratch = size_t(2) * 16 * PLD + size_t(16) * UBLD + 16 + 128;
+};
+
+// Orders this wavefront's LDS accesses around an exchange between its own lanes (LDS operations
+// of one wavefront complete in issue order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a DPP row, returned to every lane of the row.
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x124>(v);   // row_ror 4
+    v += dpp_d<0x128>(v);   // row_ror 8
+    return v;
+}
+
+// f(y) and this wavefront's tiles of M = dg I - J; d wdot/dC staged in two column windows (as
+// iteration_rows_half, whose row-pair mapping still forms the row sums sum_l JC[k][l] C_l).
+template <int NP>
+__device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, double y, double P, double dg,
+                                                d4 (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR], double &f) {
+    constexpr int W = 4, H = NP / 2, TR = TileGeom<NP>::TR, RW = TileGeom<NP>::RW;
+    using G = Grp<W>;
+    const int ns = M.nsp;
+    Mix x;
+    species_pass<W, true>(M, y, P, L, x);
+    const int tid = G::tid();
+    const int k = species_of(tid, ns);              // component mapping
+    const bool valid = k >= 0;
+    const int row = tid >> 1, half = tid & 1;       // row-pair mapping (row sums)
+    const int kr = row - 1;
+    const bool rvalid = row >= 1 && row <= ns;
+    const int wv = G::wave(), ln = G::lane(), g = ln >> 4, c16 = ln & 15;
+    double colH = 0.0, jcp = 0.0;
+#pragma unroll
+    for (int i = 0; i < RW; i++)
+#pragma unroll
+        for (int J = 0; J < TR; J++) m[i][J] = d4{0.0, 0.0, 0.0, 0.0};
+    const bool keep = L.rows != nullptr && 3 * ((M.nrxn + G::T - 1) / G::T) <= H;
+    double *cache = keep ? L.rows + opaque(tid) : nullptr;
+#pragma unroll
+    for (int w = 0; w < 2; w++) {
+        const int c0 = w * H - 1;                   // window w: matrix columns [w H, w H + H)
+        reaction_pass<W, true>(M, L, x.t, x.Ctot, c0, H, w == 0, cache, keep ? (w == 0 ? 1 : 2) : 0);
+        if (w == 0) f = finish_rhs<W>(M, L, x);
+        if (rvalid && half == w) {
+            const double *r = &L.JC[kr * L.ldj];
+            for (int j = 0; j < H; j++) {
+                const int jc = c0 + j;
+                if (jc >= 0 && jc < ns) jcp += r[j] * L.C[jc];
+            }
+        }
+        // raw window entries d wdot_(r-1) / dC_(col-1) into this wavefront's tiles
+#pragma unroll
+        for (int i = 0; i < RW; i++) {
+            const int I = wv + 4 * i;
+            if (I >= TR) break;
+#pragma unroll
+            for (int J = 0; J < TR; J++) {
+                if (16 * J + 15 < w * H || 16 * J >= w * H + H) continue;
+                const int col = 16 * J + c16;
+                const bool cin = col >= w * H && col < w * H + H && col >= 1 && col <= ns;
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int r = tile_row(I, g, v);
+                    if (cin && r >= 1 && r <= ns) m[i][J][v] = L.JC[(r - 1) * L.ldj + (col - w * H)];
+                }
+            }
+        }
+        if (valid && k + 1 >= w * H && k + 1 < w * H + H)
+            for (int r = 0; r < ns; r++) colH += L.H[r] * L.JC[r * L.ldj + (k + 1 - w * H)];
+        __syncthreads();
+    }
+    const double jrow = jcp + shfl_pair(jcp);
+    if (half == 0 && rvalid) L.RJ[row] = jrow;
+    __syncthreads();
+    // chain rule in the component mapping (as iteration_rows)
+    const double T = x.t.T, RT = M.R * T;
+    double jcc = 0.0, resid = 0.0, ra = 0.0, col0 = 0.0, TBk = 0.0, WDk = 0.0, DWTk = 0.0;
+    if (valid) {
+        TBk = L.TB[k];
+        WDk = L.WD[k];
+        DWTk = L.DWT[k];
+        jcc = L.RJ[tid] + TBk * x.Ctot;
+        colH *= RT;
+        resid = WDk - jcc;
+        ra = M.W()[k] * x.Wbar * resid / x.rho;
+        col0 = (M.W()[k] / x.rho) * (DWTk + resid * x.t.invT);
+    }
+    const double Hk = RT * x.h;
+    const double sumHTB = G::sum(valid ? Hk * TBk : 0.0, L.RED);
+    const double sumHJCC = G::sum(valid ? Hk * jcc : 0.0, L.RED);
+    const double dQT = G::sum(valid ? M.R * x.cp * WDk + Hk * (DWTk - jcc * x.t.invT) : 0.0, L.RED);
+    const double sdcp = G::sum(valid ? y * M.R * x.dcp * M.invW()[k] : 0.0, L.RED);
+    const double fT = G::bcast(f, 0, L.RED + 8);
+    const double D = x.rho * x.cpm;
+    if (valid) {
+        const double dQ = M.invW()[k] * (x.rho * (colH + sumHTB) - x.Wbar * sumHJCC);
+        const double dD = x.rho * M.invW()[k] * (M.R * x.cp - x.cpm * x.Wbar);
+        L.TROW[k] = -(dQ + fT * dD) / D;
+    }
+    if (tid < 128) {
+        L.RA[tid] = valid ? M.W()[k] : 0.0;
+        L.RB[tid] = valid ? M.W()[k] * TBk + ra : 0.0;
+        L.RC[tid] = valid ? col0 : 0.0;
+    }
+    const double J00 = -(dQT + fT * (-x.rho * x.cpm * x.t.invT + x.rho * sdcp)) / D;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RW; i++) {
+        const int I = wv + 4 * i;
+        if (I >= TR) break;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int r = tile_row(I, g, v);
+            const double alpha = L.RA[r], beta = L.RB[r], c0r = L.RC[r];
+#pragma unroll
+            for (int J = 0; J < TR; J++) {
+                const int col = 16 * J + c16;
+                double Jv;
+                if (col == 0) Jv = r == 0 ? J00 : c0r;
+                else if (r == 0) Jv = L.TROW[col - 1];
+                else Jv = L.IW[col - 1] * (alpha * m[i][J][v] + beta);
+                m[i][J][v] = (r == col ? dg : 0.0) - Jv;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Blocked Gauss-Jordan inverse in place on the tiles.  On return L.ORD[r] is the pivot order of
+// row r: tile entry (r, j) = Minv[ORD[r]][p_j], p_j the row that was pivot j.
+template <int NP>
+__device__ __forceinline__ bool gj_invert_tiles(d4 (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR], const Lds &L) {
+    using TG = TileGeom<NP>;
+    constexpr int TR = TG::TR, RW = TG::RW, PLD = TG::PLD, UBLD = TG::UBLD;
+    using G = Grp<4>;
+    const int tid = G::tid(), wv = G::wave(), ln = G::lane(), g = ln >> 4, c16 = ln & 15;
+    double *const UB = L.JC + 2 * 16 * PLD;
+    double *const PROW = UB + 16 * UBLD;
+    double *const FCOL = PROW + 16;
+    if (tid < 128) L.ORD[tid] = NP;
+    unsigned pmask = 0;          // wavefront 0: bit Ib set once row c16 + 16 Ib has been a pivot
+    bool ok = true;
+    for (int p = 0; p < TR; p++) {
+        double *const PNL = L.JC + (p & 1) * 16 * PLD;
+        // (1) the panel (tile column 0: the tile columns rotate by one per panel) into LDS,
+        //     column-major: PNL[c PLD + r] = A[r][16 p + c]
+#pragma unroll
+        for (int i = 0; i < RW; i++) {
+            const int I = wv + 4 * i;
+            if (I >= TR) break;
+#pragma unroll
+            for (int v = 0; v < 4; v++) PNL[c16 * PLD + tile_row(I, g, v)] = m[i][0][v];
+        }
+        __syncthreads();
+        // (2) wavefront 0 eliminates the panel, held as the matrix-core A operand:
+        //     lane l, slot (s, Ib) holds panel entry (16 Ib + l % 16, 4 s + l / 16)
+        if (wv == 0) {
+            double Tp[4][TR];
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int Ib = 0; Ib < TR; Ib++) Tp[s][Ib] = PNL[(4 * s + g) * PLD + 16 * Ib + c16];
+#pragma unroll
+            for (int c = 0; c < 16; c++) {
+                const int gc = c & 3, sc = c >> 2;
+                unsigned long long key = 0ull;
+                int bIb = 0;
+                if (g == gc) {
+#pragma unroll
+                    for (int Ib = 0; Ib < TR; Ib++) {
+                        const unsigned long long kk =
+                            ((pmask >> Ib) & 1u) ? 0ull : (unsigned long long)__double_as_longlong(fabs(Tp[sc][Ib]));
+                        if (kk > key) {
+                            key = kk;
+                            bIb = Ib;
+                        }
+                    }
+                }
+                const unsigned long long mx = __ockl_wfred_max_u64(key);
+                ok = ok && mx != 0ull;
+                const int src = __builtin_ctzll(__ballot(g == gc && key == mx));
+                const int Ibs = __builtin_amdgcn_readlane(bIb, src);
+                const int Rl = src & 15;
+                // pivot row (this panel's 16 entries) and pivot column through LDS
+#pragma unroll
+                for (int Ib = 0; Ib < TR; Ib++)
+                    if (Ib == Ibs && c16 == Rl) {
+#pragma unroll
+                        for (int s = 0; s < 4; s++) PROW[4 * s + g] = Tp[s][Ib];
+                    }
+                if (g == gc) {
+#pragma unroll
+                    for (int Ib = 0; Ib < TR; Ib++) FCOL[16 * Ib + c16] = Tp[sc][Ib];
+                }
+                wave_sync();
+                double ps[4], fr[TR];
+#pragma unroll
+                for (int s = 0; s < 4; s++) ps[s] = PROW[4 * s + g];
+                const double pv = PROW[c];
+#pragma unroll
+                for (int Ib = 0; Ib < TR; Ib++) fr[Ib] = FCOL[16 * Ib + c16];
+                const double rp = 1.0 / pv;
+#pragma unroll
+                for (int s = 0; s < 4; s++) ps[s] *= rp;
+#pragma unroll
+                for (int Ib = 0; Ib < TR; Ib++)
+#pragma unroll
+                    for (int s = 0; s < 4; s++) Tp[s][Ib] = fma(-fr[Ib], ps[s], Tp[s][Ib]);
+                if (g == gc) {
+#pragma unroll
+                    for (int Ib = 0; Ib < TR; Ib++) Tp[sc][Ib] = -fr[Ib] * rp;
+                }
+#pragma unroll
+                for (int Ib = 0; Ib < TR; Ib++)
+                    if (Ib == Ibs && c16 == Rl) {
+#pragma unroll
+                        for (int s = 0; s < 4; s++) Tp[s][Ib] = ps[s];
+                        if (g == gc) Tp[sc][Ib] = rp;
+                        pmask |= 1u << Ib;
+                    }
+                if (ln == 0) L.ORD[Rl + 16 * Ibs] = 16 * p + c;
+                wave_sync();
+            }
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int Ib = 0; Ib < TR; Ib++) PNL[(4 * s + g) * PLD + 16 * Ib + c16] = Tp[s][Ib];
+        }
+        __syncthreads();
+        // (3) the eliminated panel into tile column 0; the pivot rows' entries of the other
+        //     columns into UB (as U[order within the panel][column]) and zeroed in the tiles
+#pragma unroll
+        for (int i = 0; i < RW; i++) {
+            const int I = wv + 4 * i;
+            if (I >= TR) break;
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int r = tile_row(I, g, v);
+                m[i][0][v] = PNL[c16 * PLD + r];
+                const int o = L.ORD[r] - 16 * p;
+                if (o >= 0 && o < 16) {
+#pragma unroll
+                    for (int J = 1; J < TR; J++) {
+                        const int gJ = p + J < TR ? p + J : p + J - TR;
+                        UB[o * UBLD + 16 * gJ + c16] = m[i][J][v];
+                        m[i][J][v] = 0.0;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // (4) rank-16 update of the other tile columns on the matrix cores
+#pragma unroll
+        for (int i = 0; i < RW; i++) {
+            const int I = wv + 4 * i;
+            if (I >= TR) break;
+            double a[4];
+#pragma unroll
+            for (int s = 0; s < 4; s++) a[s] = PNL[(4 * s + g) * PLD + 16 * I + c16];
+#pragma unroll
+            for (int J = 1; J < TR; J++) {
+                const int gJ = p + J < TR ? p + J : p + J - TR;
+#pragma unroll
+                for (int s = 0; s < 4; s++) {
+                    const double b = UB[(4 * s + g) * UBLD + 16 * gJ + c16];
+                    m[i][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b, m[i][J], 0, 0, 0);
+                }
+            }
+        }
+        // (5) rotate the tile columns: the next panel becomes column 0
+#pragma unroll
+        for (int i = 0; i < RW; i++) {
+            const d4 t0 = m[i][0];
+#pragma unroll
+            for (int J = 0; J + 1 < TR; J++) m[i][J] = m[i][J + 1];
+            m[i][TR - 1] = t0;
+        }
+    }
+    __syncthreads();
+    return ok;
+}
+
+// x = M^-1 b with the tile inverse; b and x in the component mapping; ordr[i][v] = ORD of the
+// row held in register v of tile row i.
+template <int NP>
+__device__ __forceinline__ double gj_apply_tiles(const d4 (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR], const Lds &L,
+                                                 const int (&ordr)[TileGeom<NP>::RW][4], double b) {
+    constexpr int TR = TileGeom<NP>::TR, RW = TileGeom<NP>::RW;
+    using G = Grp<4>;
+    const int tid = G::tid(), wv = G::wave(), ln = G::lane(), c16 = ln & 15;
+    if (tid < NP && L.ORD[tid] < NP) L.BS[L.ORD[tid]] = b;
+    __syncthreads();
+    double bs[TR];
+#pragma unroll
+    for (int J = 0; J < TR; J++) bs[J] = L.BS[16 * J + c16];
+#pragma unroll
+    for (int i = 0; i < RW; i++) {
+        if (wv + 4 * i >= TR) break;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            double z = 0.0;
+#pragma unroll
+            for (int J = 0; J < TR; J++) z = fma(m[i][J][v], bs[J], z);
+            z = row16_sum(z);
+            if (c16 == 0 && ordr[i][v] < NP) L.XS[ordr[i][v]] = z;
+        }
+    }
+    __syncthreads();
+    const double xv = tid < NP ? L.XS[tid] : 0.0;
+    __syncthreads();
+    return xv;
+}
+
+template <int NP>
+struct Ros4CoopTile {
+    static constexpr double qinv = 0.25;
+    static constexpr int H = NP / 2, TR = TileGeom<NP>::TR, RW = TileGeom<NP>::RW;
+    static constexpr bool kHalf = true;
+    static constexpr size_t kRows = size_t(H) * 256;   // park-slice doubles per workgroup
+    static constexpr size_t kJcMin = TileGeom<NP>::kScratch;
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h,
+                                                double &ynew, double &e) {
+        d4 m[RW][TR];
+        double f;
+        const double dg = 1.0 / (Ros4::gamma * h);
+        iteration_tiles<NP>(M, L, y, P, dg, m, f);
+        const bool ok = gj_invert_tiles<NP>(m, L);
+        int ordr[RW][4];
+        {
+            const int wv = Grp<4>::wave(), g = Grp<4>::lane() >> 4;
+#pragma unroll
+            for (int i = 0; i < RW; i++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int I = wv + 4 * i;
+                    ordr[i][v] = I < TR ? L.ORD[tile_row(I, g, v)] : NP;
+                }
+        }
+        const double ih = 1.0 / h;
+        const double u1 = gj_apply_tiles<NP>(m, L, ordr, f);
+        double ft = rhs<4>(M, L, y + Ros4::a21 * u1, P);
+        const double u2 = gj_apply_tiles<NP>(m, L, ordr, ft + (Ros4::c21 * u1) * ih);
+        ft = rhs<4>(M, L, y + Ros4::a31 * u1 + Ros4::a32 * u2, P);
+        const double u3 = gj_apply_tiles<NP>(m, L, ordr, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
+        const double u4 =
+            gj_apply_tiles<NP>(m, L, ordr, ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
         ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
         e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
         return ok;
@@ -770,13 +1172,13 @@ __device__ __forceinline__ void integrate_reactor(const DevMech &M, const Lds &L
     }
 }
 
-template <int W, class S, int WIN>
-__global__ void __launch_bounds__(64 * W) coop_kernel(DevMech M, int64_t n, double *y, int64_t ld, const double *p,
-                                                      const double *t_end, double *t_io, double *h_io, IntOpts o,
-                                                      unsigned *queue, double *park, int32_t *status,
-                                                      int32_t *nacc, int32_t *nrej) {
+// WPE > 0: the register budget of WPE resident wavefronts per SIMD is imposed on the compiler.
+template <int W, class S, int WIN, int WPE = 0>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1, WPE > 0 ? WPE : 10)))
+coop_kernel(DevMech M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end, double *t_io,
+            double *h_io, IntOpts o, unsigned *queue, double *park, int32_t *status, int32_t *nacc, int32_t *nrej) {
     extern __shared__ double lds_raw[];
-    Lds L = carve(lds_raw, M.nsp, WIN, S::kHalf);
+    Lds L = carve(lds_raw, M.nsp, WIN, S::kHalf, S::kJcMin);
     if (park) L.rows = park + size_t(blockIdx.x) * S::kRows;
     init_lds(M, L, int(threadIdx.x), 64 * W);
     __shared__ int64_t next;
@@ -825,12 +1227,12 @@ __global__ void zero_queue_kernel(unsigned *q) { *q = 0u; }
 // Workgroups per CU of a parking kernel are capped so that the parked rows fit the workspace.
 constexpr int kParkBlocksPerCu = 2;
 
-template <int W, class S, int WIN, bool PARK>
+template <int W, class S, int WIN, bool PARK, int WPE = 0>
 int launch_kernel(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end, double *t,
                   double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc, int32_t *nrej,
                   hipStream_t s) {
-    const size_t lds = lds_doubles(M.nsp, WIN, S::kHalf) * sizeof(double);
-    auto kern = coop_kernel<W, S, WIN>;
+    const size_t lds = lds_doubles(M.nsp, WIN, S::kHalf, S::kJcMin) * sizeof(double);
+    auto kern = coop_kernel<W, S, WIN, WPE>;
     if (lds > 64 * 1024 && hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
         return CK_EHIP;
@@ -867,9 +1269,31 @@ int launch_half(const DevMech &M, int64_t n, double *y, int64_t ld, const double
                                                             nrej, s);
 }
 
+template <int NP>
+int launch_tile(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end, double *t,
+                double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc, int32_t *nrej,
+                hipStream_t s) {
+    return launch_kernel<4, Ros4CoopTile<NP>, NP / 2, true, 2>(M, n, y, ld, p, t_end, t, h, o, queue, status, nacc,
+                                                               nrej, s);
+}
+
 }  // namespace coop
 
 bool coop_supported(const DevMech &M) { return M.N <= 128; }
+bool tile_supported(const DevMech &M) { return M.N > 64 && M.N <= 128; }
+
+int launch_integrate_tile(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end,
+                          double *t, double *h, const IntOpts &o, void *ws, int32_t *status, int32_t *nacc,
+                          int32_t *nrej, hipStream_t s) {
+    unsigned *q = static_cast<unsigned *>(ws);
+    switch (((M.N + 15) / 16) * 16) {
+#define CK_TILE(NPV) \
+    case NPV: return coop::launch_tile<NPV>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+        CK_TILE(80) CK_TILE(96) CK_TILE(112) CK_TILE(128)
+#undef CK_TILE
+        default: return CK_EUNSUPPORTED;
+    }
+}
 
 namespace coop {
 template <int NP>
@@ -904,7 +1328,9 @@ int launch_jac_coop(const DevMech &M, int64_t n, const double *y, int64_t ld, co
 
 size_t coop_ws_bytes(const DevMech &M, int cus) {
     if (M.N <= 64) return 256;
-    const size_t np = size_t((M.N + 7) / 8) * 8;
+    // park slice per resident workgroup: (NP / 2) x 256 doubles, NP rounded up to 16 (the tile
+    // form's padding; at least the half-row form's, rounded up to 8)
+    const size_t np = size_t((M.N + 15) / 16) * 16;
     return 256 + size_t(cus) * coop::kParkBlocksPerCu * np * 128 * sizeof(double);
 }
 

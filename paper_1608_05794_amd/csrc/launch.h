@@ -40,6 +40,11 @@ size_t coop_ws_bytes(const DevMech &M, int cus);   // queue counter + parked inv
 int launch_integrate_coop(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end,
                           double *t, double *h, const IntOpts &o, void *ws, int32_t *status, int32_t *nacc,
                           int32_t *nrej, hipStream_t s);
+// tile form of the four-wavefront ROS4 (64 < N <= 128): blocked Gauss-Jordan on the matrix cores
+bool tile_supported(const DevMech &M);
+int launch_integrate_tile(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end,
+                          double *t, double *h, const IntOpts &o, void *ws, int32_t *status, int32_t *nacc,
+                          int32_t *nrej, hipStream_t s);
 // standalone Jacobian for 64 < N <= 128: one reactor per four-wavefront group
 int launch_jac_coop(const DevMech &M, int64_t n, const double *y, int64_t ld, const double *p, double *jac,
                     hipStream_t s);

@@ -107,6 +107,9 @@ MECHS = {
     # per-reaction scalars of the first Jacobian window do not fit its parking slice and the
     # second window recomputes them
     "M35X": dict(nsp=35, nrxn=900, n_tb=20, n_troe=10, elements="CHON", max_atoms=7, max_c=2, seed=35, dup=True),
+    # test-only: N = 71 is not a multiple of 8 or 16, so the N > 64 kernels carry padding rows
+    # and columns (and the tile form has five tile rows: uneven ownership over four wavefronts)
+    "M70": dict(nsp=70, nrxn=420, n_tb=36, n_troe=24, elements="CHON", max_atoms=8, max_c=3, seed=70),
 }
 
 

@@ -23,7 +23,7 @@ from .parity_util import jac_scaled_error, rhs_scale, state_rel_error, weighted_
 
 pytestmark = pytest.mark.gpu
 
-RECIPE = {"M13": "small", "M53": "mid", "M111": "divergent"}
+RECIPE = {"M13": "small", "M53": "mid", "M111": "divergent", "M70": "divergent", "M35X": "mid"}
 
 
 @pytest.fixture(scope="module")
@@ -62,7 +62,7 @@ def test_rhs_parity(ck, gmech, oracle_mech, name, n, kernel):
 
 
 @pytest.mark.parametrize("kernel", ["lane", "wave"])
-@pytest.mark.parametrize("name,n", [("M13", 70), ("M53", 66), ("M111", 9)])
+@pytest.mark.parametrize("name,n", [("M13", 70), ("M53", 66), ("M70", 37), ("M111", 9)])
 def test_jacobian_parity(ck, gmech, oracle_mech, name, n, kernel):
     g, om = gmech(name), oracle_mech(name)
     y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=202)
@@ -154,6 +154,43 @@ def test_ros4_group_parity(ck, gmech, oracle_mech, name, n, te):
     res, orc = _integrate_both(ck, g, om, y, P, te, "ros4", "group")
     assert np.array_equal(res["status"], orc["status"])
     _report_and_check(f"ros4 group {name}", res, orc)
+
+
+@pytest.mark.parametrize("name,n,te", [("M111", 24, 2e-7), ("M70", 70, 1e-7)])
+def test_ros4_tile_parity(ck, gmech, oracle_mech, name, n, te):
+    """Tile form (N > 64): iteration matrix in 16x16 matrix-core tiles, blocked Gauss-Jordan inverse
+    with FP64 MFMA rank-16 updates.  M70 (N = 71) pads to five tile rows (nine padding rows and
+    columns, uneven tile-row ownership across the four wavefronts)."""
+    g, om = gmech(name), oracle_mech(name)
+    y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=1013)
+    print(f"[ros4 tile {name}] {n} reactors to {te:g} s", flush=True)
+    res, orc = _integrate_both(ck, g, om, y, P, te, "ros4", "tile", max_steps=60000)
+    assert np.array_equal(res["status"], orc["status"]) and np.all(orc["status"] == 0)
+    _report_and_check(f"ros4 tile {name}", res, orc)
+
+
+def test_ros4_tile_resume_and_fixed_step(ck, gmech, oracle_mech):
+    """Tile form: fixed-step mode against the oracle (no controller, so every step is compared), and a
+    run split into bounded launches resuming from (t, h) against one call, to tolerance (its reaction
+    sums are ordered by LDS atomics across four wavefronts)."""
+    g, om = gmech("M111"), oracle_mech("M111")
+    y, P = synth.reactor_states(om.n_species, 33, "divergent", seed=1014)
+    res, orc = _integrate_both(ck, g, om, y, P, 4e-14, "ros4", "tile", h_fixed=1e-15)
+    assert np.all(np.isfinite(orc["y"]))
+    assert np.all(res["status"] == 0) and np.all(orc["status"] == 0)
+    assert np.array_equal(res["n_accept"], orc["n_accept"])
+    _report_and_check("ros4 tile M111 fixed step", res, orc)
+    whole = ck.integrate(g, dev(y), dev(P), 1e-10, kernel="tile", max_steps=60000)
+    yy, t, h = dev(y), torch.zeros(33, dtype=torch.float64, device="cuda"), torch.zeros(33, dtype=torch.float64,
+                                                                                        device="cuda")
+    for _ in range(200):
+        r = ck.integrate(g, yy, dev(P), 1e-10, kernel="tile", t=t, h=h, inplace=True, max_steps=97)
+        if not bool((r["status"] == 1).any().item()):
+            break
+    torch.cuda.synchronize()
+    assert torch.equal(r["status"], whole["status"]) and np.all(whole["status"].cpu().numpy() == 0)
+    a, b = yy.cpu().numpy(), whole["y"].cpu().numpy()
+    assert np.max(np.abs(a[0] - b[0]) / b[0]) <= 1e-6 and weighted_error(a, b) <= 1e-6
 
 
 def test_ros4_second_window_recomputes_rates(ck, gmech, oracle_mech):
