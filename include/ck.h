@@ -43,7 +43,8 @@ enum {
     CK_EPARSE = -3,        /* mechanism file malformed */
     CK_ENOMEM = -4,        /* device or host allocation failed */
     CK_EHIP = -5,          /* HIP runtime error (launch, copy) */
-    CK_EUNSUPPORTED = -6   /* option combination not implemented for this mechanism size */
+    CK_EUNSUPPORTED = -6,  /* option combination not implemented for this mechanism size */
+    CK_ETOOBIG = -7        /* the call needs more workspace than the allocation-free entry point holds */
 };
 
 /* Per-reactor integration outcome (status[] array). */
@@ -214,6 +215,23 @@ int ck_integrate_graph(const ck_mech *m, int32_t method, int64_t n, double *y, i
                        int32_t launches_per_graph, void *workspace, int32_t *status, int32_t *n_accept,
                        int32_t *n_reject, int32_t *replays, void *stream);
 size_t ck_graph_workspace_bytes(const ck_mech *m, int64_t n, const ck_opts *o);
+
+/*
+ * Allocation-free ROS4, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same contract as
+ * ck_integrate_ros4 with the workspace taken from a fixed array of the library, CK_NOALLOC_BYTES
+ * per device (held until the process ends; its address on each device is looked up once, on the
+ * first call on that device).  The call allocates nothing and returns CK_ETOOBIG when
+ * ck_workspace_bytes(m, n, o) exceeds CK_NOALLOC_BYTES (the one-reactor-per-lane kernel needs
+ * scratch linear in n; the persistent kernels need at most 64 MiB on a 256-CU device for
+ * N <= 120).  Every call on one device shares that device's array, and each call clears what it
+ * needs (its queue counter) itself: calls that overlap in time on one device race and must not be
+ * issued (serialise them on one stream).
+ */
+#define CK_NOALLOC_BYTES ((size_t)64 << 20)
+int ck_integrate_ros4_noalloc(const ck_mech *m, int64_t n, double *y, int64_t ld, const double *p,
+                              const double *t_end, double *t, double *h, const ck_opts *o, int32_t *status,
+                              int32_t *n_accept, int32_t *n_reject, void *stream);
 
 /*
  * Variants of ck_rhs_eval / ck_jacobian_eval with an explicit kernel family

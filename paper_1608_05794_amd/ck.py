@@ -37,7 +37,7 @@ _lib = None
 EXPORTS = ["ck_opts_default", "ck_strerror", "ck_mechanism_load", "ck_mechanism_free", "ck_mechanism_info",
            "ck_rhs_eval", "ck_rhs_eval_ex", "ck_jacobian_eval", "ck_jacobian_eval_ex", "ck_workspace_bytes",
            "ck_integrate_ros4", "ck_integrate_rkf45", "ck_integrate_graph",
-           "ck_graph_workspace_bytes"]
+           "ck_graph_workspace_bytes", "ck_integrate_ros4_noalloc"]
 
 
 def lib():
@@ -65,6 +65,7 @@ def lib():
         L.ck_integrate_rkf45.argtypes = sig
         L.ck_integrate_graph.argtypes = [vp, C.c_int32, i64, dp, i64, dp, dp, dp, dp, C.POINTER(Opts), C.c_int32,
                                          C.c_int32, vp, i32p, i32p, i32p, C.POINTER(C.c_int32), vp]
+        L.ck_integrate_ros4_noalloc.argtypes = [vp, i64, dp, i64, dp, dp, dp, dp, C.POINTER(Opts), i32p, i32p, i32p, vp]
         L.ck_graph_workspace_bytes.argtypes = [vp, i64, C.POINTER(Opts)]
         L.ck_graph_workspace_bytes.restype = C.c_size_t
         _lib = L
@@ -222,6 +223,27 @@ def integrate(mech, y, p, t_end, method="ros4", t=None, h=None, workspace=None, 
     _check(fn(mech.handle, n, _ptr(yy), ld, _ptr(p), _ptr(te), _ptr(t), _ptr(h), C.byref(o), _ptr(workspace),
               _ptr(st), _ptr(na), _ptr(nr), _stream(stream)))
     return dict(y=yy, t=t, h=h, status=st, n_accept=na, n_reject=nr)
+
+
+def integrate_noalloc(mech, y, p, t_end, t=None, h=None, stream=None, **opts):
+    """ROS4 through the allocation-free entry point (ck_integrate_ros4_noalloc), in place on y: the
+    library takes its workspace from a fixed device array.  Outputs (status, counters) are allocated
+    here by the caller side.  Returns dict(y, t, h, status, n_accept, n_reject)."""
+    ld = _state(y, mech.N)
+    n = y.shape[1]
+    dev = y.device
+    _vec(p, n, dev, "p")
+    _vec(t, n, dev, "t")
+    _vec(h, n, dev, "h")
+    te = t_end if torch.is_tensor(t_end) else torch.full((n,), float(t_end), dtype=torch.float64, device=dev)
+    _vec(te, n, dev, "t_end")
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+    na = torch.empty(n, dtype=torch.int32, device=dev)
+    nr = torch.empty(n, dtype=torch.int32, device=dev)
+    o = make_opts(**opts)
+    _check(lib().ck_integrate_ros4_noalloc(mech.handle, n, _ptr(y), ld, _ptr(p), _ptr(te), _ptr(t), _ptr(h),
+                                           C.byref(o), _ptr(st), _ptr(na), _ptr(nr), _stream(stream)))
+    return dict(y=y, t=t, h=h, status=st, n_accept=na, n_reject=nr)
 
 
 def integrate_graph(mech, y, p, t_end, method="ros4", launch_steps=500, launches_per_graph=8, t=None, h=None,

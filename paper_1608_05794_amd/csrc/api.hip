@@ -178,6 +178,7 @@ extern "C" const char *ck_strerror(int code) {
         case CK_ENOMEM: return "out of memory";
         case CK_EHIP: return "HIP runtime error";
         case CK_EUNSUPPORTED: return "unsupported option for this mechanism";
+        case CK_ETOOBIG: return "workspace needed exceeds the allocation-free maximum (CK_NOALLOC_BYTES)";
         default: return "unknown error";
     }
 }
@@ -420,4 +421,52 @@ extern "C" int ck_integrate_graph(const ck_mech *mc, int32_t method, int64_t n, 
     }
     if (replays) *replays = done;
     return CK_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Allocation-free ROS4: the workspace is a fixed device array of the library
+// ---------------------------------------------------------------------------------------
+namespace {
+
+__device__ __align__(256) unsigned char scratch[CK_NOALLOC_BYTES];
+
+// Device address of `scratch` on each device (each device holds its own copy), resolved once per
+// device with that device current.  The host-side symbol is not a device address.
+int scratch_ptr(int device, void **out) {
+    static std::mutex mu;
+    static std::vector<void *> ptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (device < 0) return CK_EINVAL;
+    if (int(ptr.size()) <= device) ptr.resize(size_t(device) + 1, nullptr);
+    if (!ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CK_EHIP;
+        ptr[device] = p;
+    }
+    *out = ptr[device];
+    return CK_OK;
+}
+
+}  // namespace
+
+extern "C" int ck_integrate_ros4_noalloc(const ck_mech *m, int64_t n, double *y, int64_t ld, const double *p,
+                                         const double *t_end, double *t, double *h, const ck_opts *o,
+                                         int32_t *status, int32_t *n_accept, int32_t *n_reject, void *stream) {
+    if (!m) return CK_EINVAL;
+    if (!check_state_args(m, n, y, ld, p, y)) return CK_EINVAL;
+    IntOpts io;
+    const int rc = validate_opts(o, io);
+    if (rc != CK_OK) return rc;
+    if (n == 0) return CK_OK;
+    const int kern = choose_kernel(m, 0, o);
+    if (kern < 0) return kern;
+    DeviceGuard g(m->device);
+    if (!g.ok) return CK_EHIP;
+    const size_t need = ck_workspace_bytes(m, n, o);
+    if (need == 0) return CK_EHIP;
+    if (need > CK_NOALLOC_BYTES) return CK_ETOOBIG;
+    void *ws = nullptr;
+    const int sr = scratch_ptr(m->device, &ws);
+    if (sr != CK_OK) return sr;
+    return integrate(0, m, n, y, ld, p, t_end, t, h, o, ws, status, n_accept, n_reject, stream);
 }
