@@ -324,35 +324,46 @@ def suite_batching(a):
 
 
 def suite_precision(a):
-    """FP32 LU with FP64 refinement against the all-FP64 solver (53 species): step counts and the
-    largest relative differences of T and Y (Y > 1e-12) over the whole batch, and throughput."""
+    """FP32 factorisation with FP64 refinement against the all-FP64 solver, at 53 species (wavefront
+    kernel, FP32 LU) and 111 species (tile workgroup kernel, FP32 matrix-core Gauss-Jordan): step
+    counts, FP64 refactorings (steps whose refinement stagnated), the largest relative differences of
+    T and Y (Y > 1e-12) between the two over the batch, and throughput."""
     import torch
 
     from paper_1608_05794_amd import ck, synth
-    n, te = 16384, 1e-5
-    g = ck.Mechanism(synth.mechanism_file("M53"))
-    y, P = _states(synth, torch, "M53", n, 1002)
-    res = {}
-    for prec in ("fp64", "fp32_refine"):
-        r, dt = _timed_integrate(ck, torch, g, y, P, te, kernel="wave", precision=prec)
-        res[prec] = (r, dt)
-        print(f"precision {prec}: {dt:.1f} s", file=sys.stderr, flush=True)
-    r64, r32 = res["fp64"][0], res["fp32_refine"][0]
-    T64, T32 = r64["y"][0], r32["y"][0]
-    Y64, Y32 = r64["y"][1:], r32["y"][1:]
-    mask = Y64.abs() > 1e-12
-    relY = ((Y32 - Y64).abs() / Y64.abs().clamp_min(1e-300))[mask]
-    out = {"suite": "precision", "workload": f"M53 x {n} reactors, ROS4 to {te:g} s, rtol 1e-8, atol 1e-12",
-           "data": "synthetic"}
-    for prec, (r, dt) in res.items():
-        na, nr = int(r["n_accept"].sum().item()), int(r["n_reject"].sum().item())
-        out[prec] = {"accepted": na, "rejected": nr, "seconds": dt, "reactor_steps_per_s": (na + nr) / dt,
-                     "status_ok": int((r["status"] == 0).sum().item())}
-    out["fp32_vs_fp64"] = {"max_rel_T": float(((T32 - T64).abs() / T64).max().item()),
-                           "max_rel_Y_above_1e-12": float(relY.max().item()),
-                           "median_rel_Y_above_1e-12": float(relY.median().item()),
-                           "identical_step_counts": float(((r64["n_accept"] + r64["n_reject"]) ==
-                                                           (r32["n_accept"] + r32["n_reject"])).float().mean())}
+    out = {"suite": "precision", "data": "synthetic", "dtype": "f64 (FP32 factorisation in fp32_refine)"}
+    for mech, n, te, kernel, seed in (("M53", 16384, 1e-5, "wave", 1002), ("M111", 16384, 2e-10, "tile", 1003)):
+        g = ck.Mechanism(synth.mechanism_file(mech))
+        y, P = _states(synth, torch, mech, n, seed)
+        res = {}
+        for prec in ("fp64", "fp32_refine"):
+            fb = torch.zeros(n, dtype=torch.int32, device="cuda")
+            kw = dict(n_fallback=fb) if prec != "fp64" else {}
+            _timed_integrate(ck, torch, g, y[:, :256].contiguous(), P[:256].contiguous(), te, kernel=kernel,
+                             precision=prec, max_steps=4, **({} if prec == "fp64" else
+                                                             dict(n_fallback=fb[:256])))   # warm-up
+            r, dt = _timed_integrate(ck, torch, g, y, P, te, kernel=kernel, precision=prec, **kw)
+            res[prec] = (r, dt, int(fb.sum().item()))
+            print(f"precision {mech} {prec}: {dt:.1f} s", file=sys.stderr, flush=True)
+        r64, r32 = res["fp64"][0], res["fp32_refine"][0]
+        T64, T32 = r64["y"][0], r32["y"][0]
+        Y64, Y32 = r64["y"][1:], r32["y"][1:]
+        mask = Y64.abs() > 1e-12
+        relY = ((Y32 - Y64).abs() / Y64.abs().clamp_min(1e-300))[mask]
+        row = {"workload": f"{mech} x {n} reactors, ROS4 to {te:g} s, rtol 1e-8, atol 1e-12, kernel {kernel}"}
+        for prec, (r, dt, nfb) in res.items():
+            na, nr = int(r["n_accept"].sum().item()), int(r["n_reject"].sum().item())
+            row[prec] = {"accepted": na, "rejected": nr, "seconds": dt, "reactor_steps_per_s": (na + nr) / dt,
+                         "status_ok": int((r["status"] == 0).sum().item())}
+            if prec != "fp64":
+                row[prec]["fp64_refactorings"] = nfb
+        row["fp32_vs_fp64"] = {"max_rel_T": float(((T32 - T64).abs() / T64).max().item()),
+                               "max_rel_Y_above_1e-12": float(relY.max().item()),
+                               "median_rel_Y_above_1e-12": float(relY.median().item()),
+                               "identical_step_counts": float(((r64["n_accept"] + r64["n_reject"]) ==
+                                                               (r32["n_accept"] + r32["n_reject"])).float().mean())}
+        row["speed_ratio_fp32_over_fp64"] = row["fp32_refine"]["reactor_steps_per_s"] / row["fp64"]["reactor_steps_per_s"]
+        out[mech] = row
     return out
 
 

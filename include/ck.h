@@ -57,7 +57,7 @@ enum {
 
 /* Kernel choice for the integrators. */
 enum {
-    CK_KERNEL_AUTO = 0,    /* ROS4: WAVE if N <= 64, else GROUP if N <= 128; RKF45: WAVE if N <= 128 */
+    CK_KERNEL_AUTO = 0,    /* ROS4: WAVE if N <= 64, else GROUP_TILE if N <= 128; RKF45: WAVE if N <= 128 */
     CK_KERNEL_LANE = 1,    /* one reactor per lane, all scratch in global memory (Algorithm 2 analogue) */
     CK_KERNEL_WAVE = 2,    /* one reactor per 64-lane wavefront, persistent work queue, LU in registers */
     CK_KERNEL_GROUP = 3,   /* ROS4 only: one reactor per workgroup of 1 (N <= 64) or 4 (N <= 128, matrix
@@ -94,7 +94,14 @@ enum {
 /* Precision of the Rosenbrock linear solves. */
 enum {
     CK_PREC_FP64 = 0,      /* FP64 LU and triangular solves */
-    CK_PREC_FP32_REFINE = 1 /* FP32 LU with FP64 residual refinement; wavefront kernel only */
+    CK_PREC_FP32_REFINE = 1 /* FP32 factorisation with FP64 residual refinement (RHS, Jacobian, error
+                              norm and control stay FP64): FP32 LU in the wavefront kernel (N <= 64),
+                              FP32 matrix-core Gauss-Jordan in the tile workgroup kernel
+                              (64 < N <= 128).  Each solve: x = M32^-1 b, then up to refine_sweeps
+                              corrections with FP64 residuals b - M x, done once the correction is
+                              below 2^-48 of the solution; if a correction fails to halve or the
+                              sweeps run out, that step is refactored in FP64 (counted in
+                              n_fallback).  refine_sweeps = 0: plain FP32 solves */
 };
 
 typedef struct {
@@ -110,10 +117,15 @@ typedef struct {
                               0 = as many as registers and LDS allow (larger values are clamped) */
     int32_t jacobian;      /* CK_JAC_* (ROS4 only) */
     int32_t reactor;       /* CK_REACTOR_*: with CK_REACTOR_CONST_V the p array holds densities */
+    int32_t *n_fallback;   /* CK_PREC_FP32_REFINE only, optional (NULL: not reported): device array
+                              [n] receiving, per reactor and call, the attempted steps whose FP64
+                              refinement stagnated or ran out of sweeps and that were refactored in
+                              FP64 (that step's remaining solves use the FP64 factors) */
 } ck_opts;
 
 /* Fills *o with the defaults: rtol 1e-8, atol 1e-12, h0 0, h_fixed 0, max_steps 1e6,
- * CK_KERNEL_AUTO, CK_PREC_FP64, refine_sweeps 3, blocks_per_cu 0, CK_JAC_ANALYTIC, CK_REACTOR_CONST_P. */
+ * CK_KERNEL_AUTO, CK_PREC_FP64, refine_sweeps 3, blocks_per_cu 0, CK_JAC_ANALYTIC, CK_REACTOR_CONST_P,
+ * n_fallback NULL. */
 void ck_opts_default(ck_opts *o);
 
 const char *ck_strerror(int code);

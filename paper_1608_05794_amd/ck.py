@@ -29,7 +29,8 @@ class CkError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h0", C.c_double), ("h_fixed", C.c_double),
                 ("max_steps", C.c_int64), ("kernel", C.c_int32), ("precision", C.c_int32),
-                ("refine_sweeps", C.c_int32), ("blocks_per_cu", C.c_int32), ("jacobian", C.c_int32), ("reactor", C.c_int32)]
+                ("refine_sweeps", C.c_int32), ("blocks_per_cu", C.c_int32), ("jacobian", C.c_int32), ("reactor", C.c_int32),
+                ("n_fallback", C.c_void_p)]
 
 
 _lib = None
@@ -106,7 +107,7 @@ def _vec(v, n, dev, name, dtype=torch.float64):
 
 
 def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000, kernel="auto", precision="fp64",
-              refine_sweeps=3, blocks_per_cu=0, jacobian="analytic", reactor="cp"):
+              refine_sweeps=3, blocks_per_cu=0, jacobian="analytic", reactor="cp", n_fallback=None):
     o = Opts()
     lib().ck_opts_default(C.byref(o))
     o.rtol, o.atol, o.h0, o.h_fixed, o.max_steps = rtol, atol, h0, h_fixed, max_steps
@@ -116,6 +117,7 @@ def make_opts(rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000, k
     o.blocks_per_cu = blocks_per_cu
     o.jacobian = JACOBIANS[jacobian]
     o.reactor = REACTORS[reactor]
+    o.n_fallback = n_fallback.data_ptr() if n_fallback is not None else None
     return o
 
 
@@ -210,6 +212,7 @@ def integrate(mech, y, p, t_end, method="ros4", t=None, h=None, workspace=None, 
     _vec(h, n, dev, "h")
     te = t_end if torch.is_tensor(t_end) else torch.full((n,), float(t_end), dtype=torch.float64, device=dev)
     _vec(te, n, dev, "t_end")
+    _vec(opts.get("n_fallback"), n, dev, "n_fallback", dtype=torch.int32)
     st = torch.empty(n, dtype=torch.int32, device=dev)
     na = torch.empty(n, dtype=torch.int32, device=dev)
     nr = torch.empty(n, dtype=torch.int32, device=dev)
@@ -262,6 +265,7 @@ def integrate_graph(mech, y, p, t_end, method="ros4", launch_steps=500, launches
     h = torch.zeros(n, dtype=torch.float64, device=dev) if h is None else _vec(h, n, dev, "h")
     te = t_end if torch.is_tensor(t_end) else torch.full((n,), float(t_end), dtype=torch.float64, device=dev)
     _vec(te, n, dev, "t_end")
+    _vec(opts.get("n_fallback"), n, dev, "n_fallback", dtype=torch.int32)
     st = torch.empty(n, dtype=torch.int32, device=dev)
     na = torch.empty(n, dtype=torch.int32, device=dev)
     nr = torch.empty(n, dtype=torch.int32, device=dev)

@@ -80,6 +80,7 @@ int validate_opts(const ck_opts *o, IntOpts &io) {
     io.blocks_per_cu = o->blocks_per_cu;
     io.jacobian = o->jacobian;
     io.reactor = o->reactor;
+    io.n_fallback = o->precision == CK_PREC_FP32_REFINE ? o->n_fallback : nullptr;
     return CK_OK;
 }
 
@@ -102,7 +103,7 @@ int choose_kernel(const ck_mech *m, int method, const ck_opts *o) {
         return CK_KERNEL_WAVE;
     }
     const bool group_ok = method == 0 && fp64 && coop_supported(m->dev);
-    const bool tile_ok = method == 0 && fp64 && tile_supported(m->dev);
+    const bool tile_ok = method == 0 && tile_supported(m->dev);     // FP64 or FP32 with refinement
     switch (o->kernel) {
         case CK_KERNEL_WAVE: return wave_ok ? CK_KERNEL_WAVE : CK_EUNSUPPORTED;
         case CK_KERNEL_GROUP: return group_ok ? CK_KERNEL_GROUP : CK_EUNSUPPORTED;
@@ -110,6 +111,7 @@ int choose_kernel(const ck_mech *m, int method, const ck_opts *o) {
         case CK_KERNEL_LANE: return fp64 ? CK_KERNEL_LANE : CK_EUNSUPPORTED;
         default:
             if (wave_ok) return CK_KERNEL_WAVE;
+            if (tile_ok) return CK_KERNEL_GROUP_TILE;
             if (group_ok) return CK_KERNEL_GROUP;
             return fp64 ? CK_KERNEL_LANE : CK_EUNSUPPORTED;
     }
@@ -167,6 +169,7 @@ extern "C" void ck_opts_default(ck_opts *o) {
     o->blocks_per_cu = 0;
     o->jacobian = CK_JAC_ANALYTIC;
     o->reactor = CK_REACTOR_CONST_P;
+    o->n_fallback = nullptr;
 }
 
 extern "C" const char *ck_strerror(int code) {

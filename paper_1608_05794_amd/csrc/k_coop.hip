@@ -465,7 +465,7 @@ struct Ros4Coop {
         for (int j = 0; j < NP; j++) a[j] = r[j * Grp<W>::T];
     }
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
-                                double &e) {
+                                double &e, const IntOpts &, int &) {
         double a[NP];
         double f;
         const double dg = 1.0 / (Ros4::gamma * h);
@@ -664,7 +664,7 @@ struct Ros4CoopHalf {
     static constexpr size_t kRows = size_t(H) * 256;   // park-slice doubles per workgroup
     static constexpr size_t kJcMin = 0;
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h,
-                                                double &ynew, double &e) {
+                                                double &ynew, double &e, const IntOpts &, int &) {
         double a[H];
         double f;
         const double dg = 1.0 / (Ros4::gamma * h);
@@ -700,10 +700,36 @@ struct Ros4CoopHalf {
 // ---------------------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
 // Matrix row held in register v of lane group g (= lane / 16) of tile row I.  The FP64 16x16x4
 // instruction interleaves the rows of its accumulator over the lane groups (row g + 4 v of the
-// tile; measured on the device), where the FP32 one keeps them contiguous (4 g + v).
-__device__ __forceinline__ int tile_row(int I, int g, int v) { return 16 * I + g + 4 * v; }
+// tile; measured on the device), where the FP32 one keeps them contiguous (4 g + v).  F32L selects
+// the FP32 layout.
+template <bool F32L = false>
+__device__ __forceinline__ int tile_row(int I, int g, int v) { return F32L ? 16 * I + 4 * g + v : 16 * I + g + 4 * v; }
+
+template <class T> struct TileT;
+template <> struct TileT<double> {
+    using V = d4;
+    static constexpr bool F32L = false;
+    __device__ static __forceinline__ V mfma(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ unsigned long long key(double v) {
+        return (unsigned long long)__double_as_longlong(fabs(v));
+    }
+};
+template <> struct TileT<float> {
+    using V = f4;
+    static constexpr bool F32L = true;
+    __device__ static __forceinline__ V mfma(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ unsigned long long key(float v) {
+        return (unsigned long long)__float_as_uint(fabsf(v));
+    }
+};
 
 template <int NP>
 struct TileGeom {
@@ -732,6 +758,18 @@ __device__ __forceinline__ double dpp_d(double v) {
     return __hiloint2double(hi, lo);
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float row16_sum(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x124>(v);
+    v += dpp_f<0x128>(v);
+    return v;
+}
+
 // Sum over the 16 lanes of a DPP row, returned to every lane of the row.
 __device__ __forceinline__ double row16_sum(double v) {
     v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
@@ -743,7 +781,7 @@ __device__ __forceinline__ double row16_sum(double v) {
 
 // f(y) and this wavefront's tiles of M = dg I - J; d wdot/dC staged in two column windows (as
 // iteration_rows_half, whose row-pair mapping still forms the row sums sum_l JC[k][l] C_l).
-template <int NP>
+template <int NP, bool F32L = false>
 __device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, double y, double P, double dg,
                                                 d4 (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR], double &f) {
     constexpr int W = 4, H = NP / 2, TR = TileGeom<NP>::TR, RW = TileGeom<NP>::RW;
@@ -789,7 +827,7 @@ __device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, 
                 const bool cin = col >= w * H && col < w * H + H && col >= 1 && col <= ns;
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
-                    const int r = tile_row(I, g, v);
+                    const int r = tile_row<F32L>(I, g, v);
                     if (cin && r >= 1 && r <= ns) m[i][J][v] = L.JC[(r - 1) * L.ldj + (col - w * H)];
                 }
             }
@@ -839,7 +877,7 @@ __device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, 
         if (I >= TR) break;
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            const int r = tile_row(I, g, v);
+            const int r = tile_row<F32L>(I, g, v);
             const double alpha = L.RA[r], beta = L.RB[r], c0r = L.RC[r];
 #pragma unroll
             for (int J = 0; J < TR; J++) {
@@ -857,20 +895,25 @@ __device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, 
 
 // Blocked Gauss-Jordan inverse in place on the tiles.  On return L.ORD[r] is the pivot order of
 // row r: tile entry (r, j) = Minv[ORD[r]][p_j], p_j the row that was pivot j.
-template <int NP>
-__device__ __forceinline__ bool gj_invert_tiles(d4 (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR], const Lds &L) {
+template <int NP, class T = double>
+__device__ __forceinline__ bool gj_invert_tiles(typename TileT<T>::V (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR],
+                                                const Lds &L) {
     using TG = TileGeom<NP>;
+    using TT = TileT<T>;
+    using V = typename TT::V;
+    constexpr bool F32L = TT::F32L;
     constexpr int TR = TG::TR, RW = TG::RW, PLD = TG::PLD, UBLD = TG::UBLD;
     using G = Grp<4>;
     const int tid = G::tid(), wv = G::wave(), ln = G::lane(), g = ln >> 4, c16 = ln & 15;
-    double *const UB = L.JC + 2 * 16 * PLD;
-    double *const PROW = UB + 16 * UBLD;
-    double *const FCOL = PROW + 16;
+    T *const JCT = reinterpret_cast<T *>(L.JC);
+    T *const UB = JCT + 2 * 16 * PLD;
+    T *const PROW = UB + 16 * UBLD;
+    T *const FCOL = PROW + 16;
     if (tid < 128) L.ORD[tid] = NP;
     unsigned pmask = 0;          // wavefront 0: bit Ib set once row c16 + 16 Ib has been a pivot
     bool ok = true;
     for (int p = 0; p < TR; p++) {
-        double *const PNL = L.JC + (p & 1) * 16 * PLD;
+        T *const PNL = JCT + (p & 1) * 16 * PLD;
         // (1) the panel (tile column 0: the tile columns rotate by one per panel) into LDS,
         //     column-major: PNL[c PLD + r] = A[r][16 p + c]
 #pragma unroll
@@ -878,13 +921,13 @@ __device__ __forceinline__ bool gj_invert_tiles(d4 (&m)[TileGeom<NP>::RW][TileGe
             const int I = wv + 4 * i;
             if (I >= TR) break;
 #pragma unroll
-            for (int v = 0; v < 4; v++) PNL[c16 * PLD + tile_row(I, g, v)] = m[i][0][v];
+            for (int v = 0; v < 4; v++) PNL[c16 * PLD + tile_row<F32L>(I, g, v)] = m[i][0][v];
         }
         __syncthreads();
         // (2) wavefront 0 eliminates the panel, held as the matrix-core A operand:
         //     lane l, slot (s, Ib) holds panel entry (16 Ib + l % 16, 4 s + l / 16)
         if (wv == 0) {
-            double Tp[4][TR];
+            T Tp[4][TR];
 #pragma unroll
             for (int s = 0; s < 4; s++)
 #pragma unroll
@@ -897,8 +940,7 @@ __device__ __forceinline__ bool gj_invert_tiles(d4 (&m)[TileGeom<NP>::RW][TileGe
                 if (g == gc) {
 #pragma unroll
                     for (int Ib = 0; Ib < TR; Ib++) {
-                        const unsigned long long kk =
-                            ((pmask >> Ib) & 1u) ? 0ull : (unsigned long long)__double_as_longlong(fabs(Tp[sc][Ib]));
+                        const unsigned long long kk = ((pmask >> Ib) & 1u) ? 0ull : TT::key(Tp[sc][Ib]);
                         if (kk > key) {
                             key = kk;
                             bIb = Ib;
@@ -922,13 +964,13 @@ __device__ __forceinline__ bool gj_invert_tiles(d4 (&m)[TileGeom<NP>::RW][TileGe
                     for (int Ib = 0; Ib < TR; Ib++) FCOL[16 * Ib + c16] = Tp[sc][Ib];
                 }
                 wave_sync();
-                double ps[4], fr[TR];
+                T ps[4], fr[TR];
 #pragma unroll
                 for (int s = 0; s < 4; s++) ps[s] = PROW[4 * s + g];
-                const double pv = PROW[c];
+                const T pv = PROW[c];
 #pragma unroll
                 for (int Ib = 0; Ib < TR; Ib++) fr[Ib] = FCOL[16 * Ib + c16];
-                const double rp = 1.0 / pv;
+                const T rp = T(1) / pv;
 #pragma unroll
                 for (int s = 0; s < 4; s++) ps[s] *= rp;
 #pragma unroll
@@ -964,7 +1006,7 @@ __device__ __forceinline__ bool gj_invert_tiles(d4 (&m)[TileGeom<NP>::RW][TileGe
             if (I >= TR) break;
 #pragma unroll
             for (int v = 0; v < 4; v++) {
-                const int r = tile_row(I, g, v);
+                const int r = tile_row<F32L>(I, g, v);
                 m[i][0][v] = PNL[c16 * PLD + r];
                 const int o = L.ORD[r] - 16 * p;
                 if (o >= 0 && o < 16) {
@@ -972,7 +1014,7 @@ __device__ __forceinline__ bool gj_invert_tiles(d4 (&m)[TileGeom<NP>::RW][TileGe
                     for (int J = 1; J < TR; J++) {
                         const int gJ = p + J < TR ? p + J : p + J - TR;
                         UB[o * UBLD + 16 * gJ + c16] = m[i][J][v];
-                        m[i][J][v] = 0.0;
+                        m[i][J][v] = T(0);
                     }
                 }
             }
@@ -983,7 +1025,7 @@ __device__ __forceinline__ bool gj_invert_tiles(d4 (&m)[TileGeom<NP>::RW][TileGe
         for (int i = 0; i < RW; i++) {
             const int I = wv + 4 * i;
             if (I >= TR) break;
-            double a[4];
+            T a[4];
 #pragma unroll
             for (int s = 0; s < 4; s++) a[s] = PNL[(4 * s + g) * PLD + 16 * I + c16];
 #pragma unroll
@@ -991,15 +1033,15 @@ __device__ __forceinline__ bool gj_invert_tiles(d4 (&m)[TileGeom<NP>::RW][TileGe
                 const int gJ = p + J < TR ? p + J : p + J - TR;
 #pragma unroll
                 for (int s = 0; s < 4; s++) {
-                    const double b = UB[(4 * s + g) * UBLD + 16 * gJ + c16];
-                    m[i][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b, m[i][J], 0, 0, 0);
+                    const T b = UB[(4 * s + g) * UBLD + 16 * gJ + c16];
+                    m[i][J] = TT::mfma(a[s], b, m[i][J]);
                 }
             }
         }
         // (5) rotate the tile columns: the next panel becomes column 0
 #pragma unroll
         for (int i = 0; i < RW; i++) {
-            const d4 t0 = m[i][0];
+            const V t0 = m[i][0];
 #pragma unroll
             for (int J = 0; J + 1 < TR; J++) m[i][J] = m[i][J + 1];
             m[i][TR - 1] = t0;
@@ -1011,33 +1053,104 @@ __device__ __forceinline__ bool gj_invert_tiles(d4 (&m)[TileGeom<NP>::RW][TileGe
 
 // x = M^-1 b with the tile inverse; b and x in the component mapping; ordr[i][v] = ORD of the
 // row held in register v of tile row i.
-template <int NP>
-__device__ __forceinline__ double gj_apply_tiles(const d4 (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR], const Lds &L,
-                                                 const int (&ordr)[TileGeom<NP>::RW][4], double b) {
+template <int NP, class T = double>
+__device__ __forceinline__ double gj_apply_tiles(const typename TileT<T>::V (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR],
+                                                 const Lds &L, const int (&ordr)[TileGeom<NP>::RW][4], double b) {
     constexpr int TR = TileGeom<NP>::TR, RW = TileGeom<NP>::RW;
     using G = Grp<4>;
     const int tid = G::tid(), wv = G::wave(), ln = G::lane(), c16 = ln & 15;
     if (tid < NP && L.ORD[tid] < NP) L.BS[L.ORD[tid]] = b;
     __syncthreads();
-    double bs[TR];
+    T bs[TR];
 #pragma unroll
-    for (int J = 0; J < TR; J++) bs[J] = L.BS[16 * J + c16];
+    for (int J = 0; J < TR; J++) bs[J] = T(L.BS[16 * J + c16]);
 #pragma unroll
     for (int i = 0; i < RW; i++) {
         if (wv + 4 * i >= TR) break;
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            double z = 0.0;
+            T z = T(0);
 #pragma unroll
             for (int J = 0; J < TR; J++) z = fma(m[i][J][v], bs[J], z);
             z = row16_sum(z);
-            if (c16 == 0 && ordr[i][v] < NP) L.XS[ordr[i][v]] = z;
+            if (c16 == 0 && ordr[i][v] < NP) L.XS[ordr[i][v]] = double(z);
         }
     }
     __syncthreads();
     const double xv = tid < NP ? L.XS[tid] : 0.0;
     __syncthreads();
     return xv;
+}
+
+// r = b - M x with the FP64 tiles of M (layout F32L); b and x in the component mapping.
+template <int NP, bool F32L>
+__device__ __forceinline__ double resid_tiles(const d4 (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR], const Lds &L,
+                                              double x, double b) {
+    constexpr int TR = TileGeom<NP>::TR, RW = TileGeom<NP>::RW;
+    using G = Grp<4>;
+    const int tid = G::tid(), wv = G::wave(), ln = G::lane(), g = ln >> 4, c16 = ln & 15;
+    if (tid < 128) L.VX[tid] = tid < NP ? x : 0.0;
+    __syncthreads();
+    double xs[TR];
+#pragma unroll
+    for (int J = 0; J < TR; J++) xs[J] = L.VX[16 * J + c16];
+#pragma unroll
+    for (int i = 0; i < RW; i++) {
+        const int I = wv + 4 * i;
+        if (I >= TR) break;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            double z = 0.0;
+#pragma unroll
+            for (int J = 0; J < TR; J++) z = fma(m[i][J][v], xs[J], z);
+            z = row16_sum(z);
+            if (c16 == 0) L.XS[tile_row<F32L>(I, g, v)] = z;
+        }
+    }
+    __syncthreads();
+    const double r = tid < NP ? b - L.XS[tid] : 0.0;
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double group_max_abs(double v, double *red) {
+    const double w = __longlong_as_double(
+        (long long)__ockl_wfred_max_u64((unsigned long long)__double_as_longlong(fabs(v))));
+    if (Grp<4>::lane() == 0) red[Grp<4>::wave()] = w;
+    __syncthreads();
+    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return r;
+}
+
+// Linear solves of the tile ROS4 step with the factorisation in FP32 (matrix-core FP32 updates) and
+// FP64 residual refinement (RHS, Jacobian, error norm and control stay FP64): x = M32^-1 b, then up
+// to `sweeps` corrections d = M32^-1 (b - M x), x += d, with M the FP64 matrix.  A solve is done
+// once |d| <= 2^-48 |x| (max norms over the state); it fails when a correction stops shrinking by
+// half or the sweeps run out first.
+template <int NP>
+__device__ __forceinline__ double refined_solve(const d4 (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR],
+                                                const f4 (&mf)[TileGeom<NP>::RW][TileGeom<NP>::TR], const Lds &L,
+                                                const int (&ordr)[TileGeom<NP>::RW][4], int sweeps, double b,
+                                                bool &conv) {
+    double x = gj_apply_tiles<NP, float>(mf, L, ordr, b);
+    conv = true;
+    if (sweeps <= 0) return x;
+    conv = false;
+    double dprev = INFINITY;
+    for (int s = 0; s < sweeps; s++) {
+        const double r = resid_tiles<NP, true>(m, L, x, b);
+        const double d = gj_apply_tiles<NP, float>(mf, L, ordr, r);
+        x += d;
+        const double dmax = group_max_abs(d, L.RED), xmax = group_max_abs(x, L.RED);
+        if (dmax <= 0x1p-48 * xmax) {
+            conv = true;
+            break;
+        }
+        if (!(dmax <= 0.5 * dprev)) break;        // stagnation (or not finite)
+        dprev = dmax;
+    }
+    return x;
 }
 
 template <int NP>
@@ -1048,7 +1161,7 @@ struct Ros4CoopTile {
     static constexpr size_t kRows = size_t(H) * 256;   // park-slice doubles per workgroup
     static constexpr size_t kJcMin = TileGeom<NP>::kScratch;
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h,
-                                                double &ynew, double &e) {
+                                                double &ynew, double &e, const IntOpts &, int &) {
         d4 m[RW][TR];
         double f;
         const double dg = 1.0 / (Ros4::gamma * h);
@@ -1079,6 +1192,67 @@ struct Ros4CoopTile {
     }
 };
 
+// ROS4 step of the tile form with the linear solves in FP32 and FP64 refinement (refined_solve).
+// If a solve fails to converge, the FP32 step is abandoned and this reactor-step is done again
+// with the FP64 tile step (Jacobian, FP64 matrix-core inverse, solves); `fallback` counts it.
+template <int NP>
+struct Ros4CoopTile32 {
+    static constexpr double qinv = 0.25;
+    static constexpr int H = NP / 2, TR = TileGeom<NP>::TR, RW = TileGeom<NP>::RW;
+    static constexpr bool kHalf = true;
+    static constexpr size_t kRows = size_t(H) * 256;   // park-slice doubles per workgroup
+    static constexpr size_t kJcMin = TileGeom<NP>::kScratch;
+    __device__ static __forceinline__ bool step32(const DevMech &M, const Lds &L, double y, double P, double h,
+                                                  double &ynew, double &e, int sweeps, bool &conv) {
+        d4 m[RW][TR];
+        f4 mf[RW][TR];
+        double f;
+        const double dg = 1.0 / (Ros4::gamma * h);
+        iteration_tiles<NP, true>(M, L, y, P, dg, m, f);
+#pragma unroll
+        for (int i = 0; i < RW; i++)
+#pragma unroll
+            for (int J = 0; J < TR; J++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) mf[i][J][v] = float(m[i][J][v]);
+        const bool ok = gj_invert_tiles<NP, float>(mf, L);
+        int ordr[RW][4];
+        {
+            const int wv = Grp<4>::wave(), g = Grp<4>::lane() >> 4;
+#pragma unroll
+            for (int i = 0; i < RW; i++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int I = wv + 4 * i;
+                    ordr[i][v] = I < TR ? L.ORD[tile_row<true>(I, g, v)] : NP;
+                }
+        }
+        const double ih = 1.0 / h;
+        const double u1 = refined_solve<NP>(m, mf, L, ordr, sweeps, f, conv);
+        if (!conv) return ok;
+        double ft = rhs<4>(M, L, y + Ros4::a21 * u1, P);
+        const double u2 = refined_solve<NP>(m, mf, L, ordr, sweeps, ft + (Ros4::c21 * u1) * ih, conv);
+        if (!conv) return ok;
+        ft = rhs<4>(M, L, y + Ros4::a31 * u1 + Ros4::a32 * u2, P);
+        const double u3 = refined_solve<NP>(m, mf, L, ordr, sweeps, ft + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih, conv);
+        if (!conv) return ok;
+        const double u4 = refined_solve<NP>(m, mf, L, ordr, sweeps,
+                                            ft + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih, conv);
+        if (!conv) return ok;
+        ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
+        e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
+        return ok;
+    }
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h,
+                                                double &ynew, double &e, const IntOpts &o, int &fallback) {
+        bool conv = true;
+        const bool ok = step32(M, L, y, P, h, ynew, e, o.refine_sweeps, conv);
+        if (conv) return ok;
+        fallback++;
+        return Ros4CoopTile<NP>::step(M, L, y, P, h, ynew, e, o, fallback);
+    }
+};
+
 // Algorithm 1 for one reactor on the group (same specification as the other kernels).
 template <int W, class S>
 __device__ __forceinline__ void integrate_reactor(const DevMech &M, const Lds &L, int64_t r, double *y, int64_t ld, const double *p,
@@ -1094,7 +1268,7 @@ __device__ __forceinline__ void integrate_reactor(const DevMech &M, const Lds &L
     double t = t_io ? t_io[r] : 0.0;
     double h = h_io ? h_io[r] : 0.0;
     int st = CK_ST_OK;
-    int na = 0, nj = 0;
+    int na = 0, nj = 0, fb = 0;
     auto all_finite = [&](double v) {
         return G::sum((mine && !isfinite(v)) ? 1.0 : 0.0, L.RED) == 0.0;
     };
@@ -1135,7 +1309,7 @@ __device__ __forceinline__ void integrate_reactor(const DevMech &M, const Lds &L
             const bool clipped = (t + h >= te);
             const double hs = clipped ? te - t : h;
             double yn, e;
-            const bool ok = S::step(M, L, yv, P, hs, yn, e);
+            const bool ok = S::step(M, L, yv, P, hs, yn, e, o, fb);
             double err;
             if (o.h_fixed > 0.0)
                 err = 0.0;
@@ -1169,6 +1343,7 @@ __device__ __forceinline__ void integrate_reactor(const DevMech &M, const Lds &L
         status[r] = st;
         nacc[r] = na;
         nrej[r] = nj;
+        if (o.n_fallback) o.n_fallback[r] = fb;
     }
 }
 
@@ -1277,6 +1452,14 @@ int launch_tile(const DevMech &M, int64_t n, double *y, int64_t ld, const double
                                                                nrej, s);
 }
 
+template <int NP>
+int launch_tile32(const DevMech &M, int64_t n, double *y, int64_t ld, const double *p, const double *t_end,
+                  double *t, double *h, const IntOpts &o, unsigned *queue, int32_t *status, int32_t *nacc,
+                  int32_t *nrej, hipStream_t s) {
+    return launch_kernel<4, Ros4CoopTile32<NP>, NP / 2, true, 2>(M, n, y, ld, p, t_end, t, h, o, queue, status,
+                                                                 nacc, nrej, s);
+}
+
 }  // namespace coop
 
 bool coop_supported(const DevMech &M) { return M.N <= 128; }
@@ -1286,6 +1469,15 @@ int launch_integrate_tile(const DevMech &M, int64_t n, double *y, int64_t ld, co
                           double *t, double *h, const IntOpts &o, void *ws, int32_t *status, int32_t *nacc,
                           int32_t *nrej, hipStream_t s) {
     unsigned *q = static_cast<unsigned *>(ws);
+    if (o.precision == CK_PREC_FP32_REFINE) {
+        switch (((M.N + 15) / 16) * 16) {
+#define CK_TILE32(NPV) \
+    case NPV: return coop::launch_tile32<NPV>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);
+            CK_TILE32(80) CK_TILE32(96) CK_TILE32(112) CK_TILE32(128)
+#undef CK_TILE32
+            default: return CK_EUNSUPPORTED;
+        }
+    }
     switch (((M.N + 15) / 16) * 16) {
 #define CK_TILE(NPV) \
     case NPV: return coop::launch_tile<NPV>(M, n, y, ld, p, t_end, t, h, o, q, status, nacc, nrej, s);

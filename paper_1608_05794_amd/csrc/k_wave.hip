@@ -578,7 +578,8 @@ __device__ __forceinline__ void unpark_rows(const Lds &L, double (&a)[NP]) {
     for (int j = 0; j < NP; j++) a[j] = r[j * 64];
 }
 
-template <int NP>
+// FULLJC: d wdot/dC staged whole (the FP32-mode LDS layout), no column windows.
+template <int NP, bool FULLJC = false>
 struct Ros4Wave {
     using SH = WaveShape<NP>;
     static constexpr double qinv = 0.25;
@@ -587,7 +588,7 @@ struct Ros4Wave {
         double a[NP];
         double f;
         const double dg = 1.0 / (Ros4::gamma * h);
-        if (SH::NWIN == 1) {
+        if (SH::NWIN == 1 || FULLJC) {
             JRow jr;
             jac_rows<NP, double>(M, L, y, P, dg, a, f, jr);
         } else {
@@ -734,14 +735,15 @@ __device__ __forceinline__ float lu_solve32(const float (&a)[NP], const LU32<NP>
 }
 
 // ROS4 step whose linear solves use an FP32 LU of M = I/(gamma h) - J, refined with FP64
-// residuals r = b - M x (M x formed from the FP64 Jacobian pieces).  Refinement stops once the
-// correction is below 2^-48 of the solution; if after the allowed sweeps it is still above
-// 1e-10 of the solution, the step is reported as failed (rejected, so h shrinks and M becomes
-// better conditioned).  With zero sweeps the FP32 solutions are used as they are.
+// residuals r = b - M x (M x formed from the FP64 Jacobian pieces).  A solve is done once the
+// correction is below 2^-48 of the solution.  If a correction fails to halve the previous one, or
+// the allowed sweeps run out first, the FP32 step is abandoned and the reactor-step is done again
+// in FP64 (rows formed in FP64 from the full staged d wdot/dC, FP64 LU); `fb` counts such steps.
+// With zero sweeps the FP32 solutions are used as they are.
 template <int NP>
 struct Ros4Wave32 {
-    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
-                                double &e, int sweeps) {
+    __device__ static __forceinline__ bool step32(const DevMech &M, const Lds &L, double y, double P, double h,
+                                                  double &ynew, double &e, int sweeps, bool &conv) {
         float a[NP];
         double f;
         JRow jr;
@@ -749,34 +751,48 @@ struct Ros4Wave32 {
         jac_rows<NP, float>(M, L, y, P, dg, a, f, jr);
         LU32<NP> lu;
         lu_factor32<NP>(a, lu);
-        bool ok = lu.ok;
+        const bool ok = lu.ok;
+        conv = true;
         auto solve = [&](double b) -> double {
             double x = double(lu_solve32<NP>(a, lu, float(b)));
             if (sweeps <= 0) return x;
-            double dmax = 0.0, xmax = 0.0;
+            double dprev = INFINITY;
             for (int s = 0; s < sweeps; s++) {
                 const double r = b - (dg * x - jac_times(M, L, jr, x));
                 const double d = double(lu_solve32<NP>(a, lu, float(r)));
                 x += d;
-                dmax = wmax_abs(d);
-                xmax = wmax_abs(x);
-                if (dmax <= 0x1p-48 * xmax) break;
+                const double dmax = wmax_abs(d), xmax = wmax_abs(x);
+                if (dmax <= 0x1p-48 * xmax) return x;
+                if (!(dmax <= 0.5 * dprev)) break;      // stagnation (or not finite)
+                dprev = dmax;
             }
-            if (!(dmax <= 1e-10 * xmax)) ok = false;
+            conv = false;
             return x;
         };
         const double ih = 1.0 / h;
         const double u1 = solve(f);
+        if (!conv) return ok;
         double yt[1] = {y + Ros4::a21 * u1}, ft[1];
         rhs_wave<1>(M, L, yt, P, ft);
         const double u2 = solve(ft[0] + (Ros4::c21 * u1) * ih);
+        if (!conv) return ok;
         yt[0] = y + Ros4::a31 * u1 + Ros4::a32 * u2;
         rhs_wave<1>(M, L, yt, P, ft);
         const double u3 = solve(ft[0] + (Ros4::c31 * u1 + Ros4::c32 * u2) * ih);
+        if (!conv) return ok;
         const double u4 = solve(ft[0] + (Ros4::c41 * u1 + Ros4::c42 * u2 + Ros4::c43 * u3) * ih);
+        if (!conv) return ok;
         ynew = y + Ros4::m1 * u1 + Ros4::m2 * u2 + Ros4::m3 * u3 + Ros4::m4 * u4;
         e = Ros4::e1 * u1 + Ros4::e2 * u2 + Ros4::e3 * u3 + Ros4::e4 * u4;
         return ok;
+    }
+    __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, double y, double P, double h, double &ynew,
+                                double &e, int sweeps, int &fb) {
+        bool conv = true;
+        const bool ok = step32(M, L, y, P, h, ynew, e, sweeps, conv);
+        if (conv) return ok;
+        fb++;
+        return Ros4Wave<NP, true>::step(M, L, y, P, h, ynew, e);
     }
 };
 
@@ -858,7 +874,7 @@ struct Ros4Adapter {
     static constexpr int PARK_ROWS = NP;
     static constexpr double qinv = 0.25;
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P, double h,
-                                double (&yn)[1], double (&e)[1], const IntOpts &) {
+                                double (&yn)[1], double (&e)[1], const IntOpts &, int &) {
         return Ros4Wave<NP>::step(M, L, y[0], P, h, yn[0], e[0]);
     }
 };
@@ -873,7 +889,7 @@ struct Ros4AdapterFD {
     static constexpr int PARK_ROWS = NP;
     static constexpr double qinv = 0.25;
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P,
-                                                double h, double (&yn)[1], double (&e)[1], const IntOpts &o) {
+                                                double h, double (&yn)[1], double (&e)[1], const IntOpts &o, int &) {
         return Ros4WaveFD<NP>::step(M, L, y[0], P, h, yn[0], e[0], o);
     }
 };
@@ -888,8 +904,8 @@ struct Ros4Adapter32 {
     static constexpr int PARK_ROWS = 0;
     static constexpr double qinv = 0.25;
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, const double (&y)[1], double P, double h,
-                                double (&yn)[1], double (&e)[1], const IntOpts &o) {
-        return Ros4Wave32<NP>::step(M, L, y[0], P, h, yn[0], e[0], o.refine_sweeps);
+                                double (&yn)[1], double (&e)[1], const IntOpts &o, int &fb) {
+        return Ros4Wave32<NP>::step(M, L, y[0], P, h, yn[0], e[0], o.refine_sweeps, fb);
     }
 };
 
@@ -911,7 +927,7 @@ __device__ __forceinline__ void integrate_reactor(const DevMech &M, const Lds &L
     double t = t_io ? t_io[r] : 0.0;
     double h = h_io ? h_io[r] : 0.0;
     int st = CK_ST_OK;
-    int na = 0, nj = 0;
+    int na = 0, nj = 0, fb = 0;
     if (!all_finite<RPL>(N, yv)) {
         st = CK_ST_NONFINITE;
         h = 0.0;
@@ -969,7 +985,7 @@ __device__ __forceinline__ void integrate_reactor(const DevMech &M, const Lds &L
             const bool clipped = (t + h >= te);
             const double hs = clipped ? te - t : h;
             double yn[RPL], e[RPL];
-            const bool ok = S::step(M, L, yv, P, hs, yn, e, o);
+            const bool ok = S::step(M, L, yv, P, hs, yn, e, o, fb);
             double err;
             if (o.h_fixed > 0.0)
                 err = 0.0;
@@ -1007,6 +1023,7 @@ __device__ __forceinline__ void integrate_reactor(const DevMech &M, const Lds &L
         status[r] = st;
         nacc[r] = na;
         nrej[r] = nj;
+        if (o.n_fallback) o.n_fallback[r] = fb;
     }
 }
 
@@ -1020,7 +1037,7 @@ struct Rkf45S {
     static constexpr int PARK_ROWS = 0;
     static constexpr double qinv = 0.2;
     __device__ static __forceinline__ bool step(const DevMech &M, const Lds &L, const double (&y)[R], double P, double h,
-                                double (&yn)[R], double (&e)[R], const IntOpts &) {
+                                double (&yn)[R], double (&e)[R], const IntOpts &, int &) {
         return Rkf45Wave<R>::step(M, L, y, P, h, yn, e);
     }
 };

@@ -11,6 +11,7 @@ struct IntOpts {
     int64_t max_steps;
     int32_t precision, refine_sweeps, blocks_per_cu, jacobian;
     int32_t reactor;   // 0 constant pressure, 1 constant volume
+    int32_t *n_fallback;   // optional [n]: FP32-mode steps refactored in FP64 (written per call)
 };
 
 // lane-per-reactor family (k_lane.hip)

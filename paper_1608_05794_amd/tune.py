@@ -22,6 +22,9 @@ def candidates(n_state, method="ros4", precision="fp64", max_blocks_per_cu=8):
     if wave_ok:
         for b in range(max_blocks_per_cu, 0, -1):
             out.append({"kernel": "wave", "blocks_per_cu": b})
+    if method == "ros4" and precision == "fp64" and 64 < n_state <= 128:
+        for b in (2, 1):
+            out.append({"kernel": "tile", "blocks_per_cu": b})
     if method == "ros4" and precision == "fp64" and n_state <= 128:
         for b in (2, 1):
             out.append({"kernel": "group", "blocks_per_cu": b})

@@ -20,6 +20,7 @@ CASES = [
     ("M53", 53, "mid", 1002, 131072, 1e-10, "wave", "fp32_refine", 500),
     ("M111", 111, "divergent", 1003, 262144, 1e-12, "group", "fp64", 200),
     ("M111", 111, "divergent", 1003, 262144, 1e-12, "tile", "fp64", 200),
+    ("M111", 111, "divergent", 1003, 262144, 1e-12, "tile", "fp32_refine", 200),
 ]
 
 

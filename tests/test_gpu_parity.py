@@ -290,18 +290,45 @@ def test_concurrent_streams_without_workspace(ck, gmech, name, kernel):
                 assert eT <= 1e-6 and ew <= 1e-5
 
 
-@pytest.mark.parametrize("name,n,te", [("M13", 512, 1e-4), ("M53", 67, 2e-6)])
-def test_ros4_fp32_refined(ck, gmech, oracle_mech, name, n, te):
-    """FP32 LU with FP64 residual refinement (<= 3 sweeps); RHS, Jacobian, error norm and control stay FP64.
-    Compared against the all-FP64 oracle; step counts are reported against the FP64 solver."""
+@pytest.mark.parametrize("name,n,te,kernel", [("M13", 512, 1e-4, "wave"), ("M53", 67, 2e-6, "wave"),
+                                              ("M70", 40, 1e-7, "tile"), ("M111", 24, 2e-7, "tile")])
+def test_ros4_fp32_refined(ck, gmech, oracle_mech, name, n, te, kernel):
+    """FP32 factorisation with FP64 residual refinement (<= 3 sweeps; FP32 LU in the wavefront kernel,
+    FP32 matrix-core Gauss-Jordan in the tile kernel for N > 64); RHS, Jacobian, error norm and control
+    stay FP64.  Compared against the all-FP64 oracle; step counts and FP64 refactorings reported."""
     g, om = gmech(name), oracle_mech(name)
     y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=1008)
-    res, orc = _integrate_both(ck, g, om, y, P, te, "ros4", "wave", precision="fp32_refine", refine_sweeps=3)
-    assert np.array_equal(res["status"], orc["status"])
+    fb = torch.zeros(n, dtype=torch.int32, device="cuda")
+    print(f"[ros4 fp32+refine {name}] {n} reactors to {te:g} s ({kernel})", flush=True)
+    res, orc = _integrate_both(ck, g, om, y, P, te, "ros4", kernel, precision="fp32_refine", refine_sweeps=3,
+                               n_fallback=fb, max_steps=60000)
+    assert np.array_equal(res["status"], orc["status"]) and np.all(orc["status"] == 0)
     dacc = (res["n_accept"] - orc["n_accept"]).mean()
     drej = (res["n_reject"] - orc["n_reject"]).mean()
-    print(f"[ros4 fp32+refine {name}] mean extra accepted {dacc:.2f}, mean extra rejected {drej:.2f}", flush=True)
+    nfb = int(fb.sum().item())
+    steps = int((res["n_accept"] + res["n_reject"]).sum())
+    print(f"[ros4 fp32+refine {name}] mean extra accepted {dacc:.2f}, mean extra rejected {drej:.2f}, "
+          f"FP64 refactorings {nfb} of {steps} steps", flush=True)
     _report_and_check(f"ros4 fp32+refine {name}", res, orc)
+
+
+@pytest.mark.parametrize("name,n,te,kernel", [("M53", 40, 2e-7, "wave"), ("M111", 12, 2e-8, "tile")])
+def test_ros4_fp32_fallback_path(ck, gmech, oracle_mech, name, n, te, kernel):
+    """The FP64 refactoring path of the refined mode, forced from the host: with one refinement sweep a
+    solve rarely reaches the 2^-48 stopping test, so most steps are redone in FP64 and counted; the
+    result still meets the FP64 parity bar."""
+    g, om = gmech(name), oracle_mech(name)
+    y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=1015)
+    fb = torch.zeros(n, dtype=torch.int32, device="cuda")
+    print(f"[ros4 fp32 fallback {name}] {n} reactors to {te:g} s ({kernel})", flush=True)
+    res, orc = _integrate_both(ck, g, om, y, P, te, "ros4", kernel, precision="fp32_refine", refine_sweeps=1,
+                               n_fallback=fb, max_steps=60000)
+    assert np.array_equal(res["status"], orc["status"]) and np.all(orc["status"] == 0)
+    steps = res["n_accept"] + res["n_reject"]
+    nfb = fb.cpu().numpy()
+    print(f"[ros4 fp32 fallback {name}] FP64 refactorings {nfb.sum()} of {steps.sum()} steps", flush=True)
+    assert nfb.sum() > 0 and np.all(nfb <= steps)
+    _report_and_check(f"ros4 fp32 fallback {name}", res, orc)
 
 
 @pytest.mark.parametrize("name,n,te", [("M13", 256, 1e-5), ("M53", 40, 5e-7)])
