@@ -30,7 +30,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "reactors/s integrated (ROS4, rtol 1e-8), RHS evals/s, p50/p99 solve latency"
 KERNEL_NAMES = {"wave": "integrate_wave_kernel<Ros4Adapter>", "auto": "integrate_wave_kernel<Ros4Adapter>",
-                "group": "coop_kernel<Ros4Coop>", "lane": "integrate_lane_kernel<0>"}
+                "group": "coop_kernel<4, Ros4CoopHalf>", "tile": "coop_kernel<4, Ros4CoopTile>",
+                "lane": "integrate_lane_kernel<0>"}
 PEAK_FP64_VECTOR = 78.6e12         # FLOP/s, MI355X FP64 vector (VALU)
 # HBM traffic of the integrator kernel from two rocprofv3 --pmc runs of the default command (one
 # with FETCH_SIZE, one with WRITE_SIZE; KiB per dispatch averaged over its launches), each scaled
@@ -117,7 +118,7 @@ def parse():
     ap.add_argument("--mech", default="M53")
     ap.add_argument("--reactors", type=int, default=131072)
     ap.add_argument("--t-end", type=float, default=1e-3)
-    ap.add_argument("--kernel", default="wave", choices=["wave", "lane", "group", "auto"])
+    ap.add_argument("--kernel", default="wave", choices=["wave", "lane", "group", "tile", "auto"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refine"])
     ap.add_argument("--launch-steps", type=int, default=2000,
                     help="attempted steps per reactor per kernel launch; launches resume from (t, h)")
@@ -386,7 +387,7 @@ def suite_serving(a):
         r.t_end *= a.serve_t_scale
     pool_opts = {}
     if a.serve_precision != "fp64":
-        pool_opts = {m: {"precision": a.serve_precision} for m in ("M13", "M53")}
+        pool_opts = {m: {"precision": a.serve_precision} for m in ("M13", "M53", "M111")}
     srv = serve.Server(mechs, hbm_budget=200e9, launch_steps=a.serve_launch_steps, pool_opts=pool_opts)
     by_mech = {m: sum(1 for r in reqs if r.mech == m) for m in mechs}
     t0 = time.perf_counter()
@@ -722,7 +723,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": measured_traffic(a),
                      "traffic_unit": "bytes per launch",
-                     "kernel": KERNEL_NAMES[a.kernel].replace("Adapter", "Adapter32" if a.precision != "fp64" else "Adapter"),
+                     "kernel": (KERNEL_NAMES[a.kernel].replace("Adapter", "Adapter32").replace("CoopTile", "CoopTile32")
+                                if a.precision != "fp64" else KERNEL_NAMES[a.kernel]),
                      "launches": launches,
                      "avg_launch_ms": 1e3 * kernel_s / launches,
                      "flops_per_step_of_batch": flops_launch, "kernel_s": kernel_s,

@@ -22,6 +22,7 @@
 #include "launch.h"
 
 extern "C" __device__ unsigned long long __ockl_wfred_max_u64(unsigned long long);
+extern "C" __device__ unsigned __ockl_wfred_max_u32(unsigned);
 extern "C" __device__ double __ockl_wfred_add_f64(double);
 
 namespace ck {
@@ -716,8 +717,15 @@ template <> struct TileT<double> {
     __device__ static __forceinline__ V mfma(double a, double b, V c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-    __device__ static __forceinline__ unsigned long long key(double v) {
-        return (unsigned long long)__double_as_longlong(fabs(v));
+    // pivot-search key: the high word of |v| (ordered like |v|; values within a relative 2^-20 of
+    // each other may tie, and then the first row in lane order is taken)
+    __device__ static __forceinline__ unsigned key(double v) { return unsigned(__double2hiint(fabs(v))); }
+    __device__ static __forceinline__ double readlane(double v, int src) { return readlane_d(v, src); }
+    // 1 / x from the hardware estimate and two Newton-Raphson steps (within an ulp)
+    __device__ static __forceinline__ double recip(double x) {
+        double r = __builtin_amdgcn_rcp(x);
+        r = fma(fma(-x, r, 1.0), r, r);
+        return fma(fma(-x, r, 1.0), r, r);
     }
 };
 template <> struct TileT<float> {
@@ -726,8 +734,13 @@ template <> struct TileT<float> {
     __device__ static __forceinline__ V mfma(float a, float b, V c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
-    __device__ static __forceinline__ unsigned long long key(float v) {
-        return (unsigned long long)__float_as_uint(fabsf(v));
+    __device__ static __forceinline__ unsigned key(float v) { return __float_as_uint(fabsf(v)); }
+    __device__ static __forceinline__ float readlane(float v, int src) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+    }
+    __device__ static __forceinline__ float recip(float x) {
+        const float r = __builtin_amdgcn_rcpf(x);
+        return fmaf(fmaf(-x, r, 1.0f), r, r);
     }
 };
 
@@ -738,9 +751,8 @@ struct TileGeom {
     static constexpr int RW = (TR + 3) / 4;       // tile rows per wavefront
     static constexpr int PLD = NP + 4;            // column stride of an LDS panel buffer (doubles)
     static constexpr int UBLD = NP;               // row stride of the pivot-row buffer
-    // scratch carved from the JC region: panel buffers [2][16][PLD], pivot rows [16][UBLD], the
-    // pivot row and the pivot column of one elimination step [16 + 128]
-    static constexpr size_t kScratch = size_t(2) * 16 * PLD + size_t(16) * UBLD + 16 + 128;
+    // scratch carved from the JC region: panel buffers [2][16][PLD] and pivot rows [16][UBLD]
+    static constexpr size_t kScratch = size_t(2) * 16 * PLD + size_t(16) * UBLD;
 };
 
 // Orders this wavefront's LDS accesses around an exchange between its own lanes (LDS operations
@@ -907,10 +919,8 @@ __device__ __forceinline__ bool gj_invert_tiles(typename TileT<T>::V (&m)[TileGe
     const int tid = G::tid(), wv = G::wave(), ln = G::lane(), g = ln >> 4, c16 = ln & 15;
     T *const JCT = reinterpret_cast<T *>(L.JC);
     T *const UB = JCT + 2 * 16 * PLD;
-    T *const PROW = UB + 16 * UBLD;
-    T *const FCOL = PROW + 16;
     if (tid < 128) L.ORD[tid] = NP;
-    unsigned pmask = 0;          // wavefront 0: bit Ib set once row c16 + 16 Ib has been a pivot
+    unsigned pmask = 0;          // wavefront 0: bit 0 (1) set once row l (l + 64) has been a pivot
     bool ok = true;
     for (int p = 0; p < TR; p++) {
         T *const PNL = JCT + (p & 1) * 16 * PLD;
@@ -924,78 +934,67 @@ __device__ __forceinline__ bool gj_invert_tiles(typename TileT<T>::V (&m)[TileGe
             for (int v = 0; v < 4; v++) PNL[c16 * PLD + tile_row<F32L>(I, g, v)] = m[i][0][v];
         }
         __syncthreads();
-        // (2) wavefront 0 eliminates the panel, held as the matrix-core A operand:
-        //     lane l, slot (s, Ib) holds panel entry (16 Ib + l % 16, 4 s + l / 16)
+        // (2) wavefront 0 eliminates the panel with one panel row per lane (rows l and l + 64): the
+        //     pivot search is a wavefront reduction, the pivot row reaches every lane by lane reads
+        //     (scalar operands of the updates), and the pivot reciprocal comes from the hardware
+        //     estimate refined by Newton steps
         if (wv == 0) {
-            T Tp[4][TR];
-#pragma unroll
-            for (int s = 0; s < 4; s++)
-#pragma unroll
-                for (int Ib = 0; Ib < TR; Ib++) Tp[s][Ib] = PNL[(4 * s + g) * PLD + 16 * Ib + c16];
+            const bool has1 = ln + 64 < NP;
+            T R0[16], R1[16];
 #pragma unroll
             for (int c = 0; c < 16; c++) {
-                const int gc = c & 3, sc = c >> 2;
-                unsigned long long key = 0ull;
-                int bIb = 0;
-                if (g == gc) {
-#pragma unroll
-                    for (int Ib = 0; Ib < TR; Ib++) {
-                        const unsigned long long kk = ((pmask >> Ib) & 1u) ? 0ull : TT::key(Tp[sc][Ib]);
-                        if (kk > key) {
-                            key = kk;
-                            bIb = Ib;
-                        }
-                    }
-                }
-                const unsigned long long mx = __ockl_wfred_max_u64(key);
-                ok = ok && mx != 0ull;
-                const int src = __builtin_ctzll(__ballot(g == gc && key == mx));
-                const int Ibs = __builtin_amdgcn_readlane(bIb, src);
-                const int Rl = src & 15;
-                // pivot row (this panel's 16 entries) and pivot column through LDS
-#pragma unroll
-                for (int Ib = 0; Ib < TR; Ib++)
-                    if (Ib == Ibs && c16 == Rl) {
-#pragma unroll
-                        for (int s = 0; s < 4; s++) PROW[4 * s + g] = Tp[s][Ib];
-                    }
-                if (g == gc) {
-#pragma unroll
-                    for (int Ib = 0; Ib < TR; Ib++) FCOL[16 * Ib + c16] = Tp[sc][Ib];
-                }
-                wave_sync();
-                T ps[4], fr[TR];
-#pragma unroll
-                for (int s = 0; s < 4; s++) ps[s] = PROW[4 * s + g];
-                const T pv = PROW[c];
-#pragma unroll
-                for (int Ib = 0; Ib < TR; Ib++) fr[Ib] = FCOL[16 * Ib + c16];
-                const T rp = T(1) / pv;
-#pragma unroll
-                for (int s = 0; s < 4; s++) ps[s] *= rp;
-#pragma unroll
-                for (int Ib = 0; Ib < TR; Ib++)
-#pragma unroll
-                    for (int s = 0; s < 4; s++) Tp[s][Ib] = fma(-fr[Ib], ps[s], Tp[s][Ib]);
-                if (g == gc) {
-#pragma unroll
-                    for (int Ib = 0; Ib < TR; Ib++) Tp[sc][Ib] = -fr[Ib] * rp;
-                }
-#pragma unroll
-                for (int Ib = 0; Ib < TR; Ib++)
-                    if (Ib == Ibs && c16 == Rl) {
-#pragma unroll
-                        for (int s = 0; s < 4; s++) Tp[s][Ib] = ps[s];
-                        if (g == gc) Tp[sc][Ib] = rp;
-                        pmask |= 1u << Ib;
-                    }
-                if (ln == 0) L.ORD[Rl + 16 * Ibs] = 16 * p + c;
-                wave_sync();
+                R0[c] = PNL[c * PLD + ln];
+                R1[c] = has1 ? PNL[c * PLD + ln + 64] : T(0);
             }
 #pragma unroll
-            for (int s = 0; s < 4; s++)
+            for (int c = 0; c < 16; c++) {
+                const unsigned k0 = (pmask & 1u) ? 0u : TT::key(R0[c]);
+                const unsigned k1 = ((pmask & 2u) || !has1) ? 0u : TT::key(R1[c]);
+                const bool w1 = k1 > k0;
+                const unsigned key = w1 ? k1 : k0;
+                const unsigned mx = __ockl_wfred_max_u32(key);
+                ok = ok && mx != 0u;
+                const int src = __builtin_ctzll(__ballot(key == mx));
+                const int sel1 = __builtin_amdgcn_readlane(int(w1), src);
+                const bool piv = ln == src;
+                // each pivot-row entry is read from the pivot lane just before its column is
+                // updated (the pivot row itself becomes that entry times 1 / pivot)
+                if (sel1) {
+                    const T rp = TT::recip(TT::readlane(R1[c], src));
+                    const T g0 = -R0[c] * rp, g1 = -R1[c] * rp;
 #pragma unroll
-                for (int Ib = 0; Ib < TR; Ib++) PNL[(4 * s + g) * PLD + 16 * Ib + c16] = Tp[s][Ib];
+                    for (int j = 0; j < 16; j++) {
+                        if (j == c) continue;
+                        const T pj = TT::readlane(R1[j], src);
+                        R0[j] = fma(g0, pj, R0[j]);
+                        const T u = fma(g1, pj, R1[j]);
+                        R1[j] = piv ? pj * rp : u;
+                    }
+                    R0[c] = g0;
+                    R1[c] = piv ? rp : g1;
+                    if (piv) pmask |= 2u;
+                } else {
+                    const T rp = TT::recip(TT::readlane(R0[c], src));
+                    const T g0 = -R0[c] * rp, g1 = -R1[c] * rp;
+#pragma unroll
+                    for (int j = 0; j < 16; j++) {
+                        if (j == c) continue;
+                        const T pj = TT::readlane(R0[j], src);
+                        const T u = fma(g0, pj, R0[j]);
+                        R0[j] = piv ? pj * rp : u;
+                        R1[j] = fma(g1, pj, R1[j]);
+                    }
+                    R0[c] = piv ? rp : g0;
+                    R1[c] = g1;
+                    if (piv) pmask |= 1u;
+                }
+                if (ln == 0) L.ORD[src + 64 * sel1] = 16 * p + c;
+            }
+#pragma unroll
+            for (int c = 0; c < 16; c++) {
+                PNL[c * PLD + ln] = R0[c];
+                if (has1) PNL[c * PLD + ln + 64] = R1[c];
+            }
         }
         __syncthreads();
         // (3) the eliminated panel into tile column 0; the pivot rows' entries of the other
