@@ -42,11 +42,11 @@ TRAFFIC_REF = {
     "sources": ["paper_1608_05794_amd/csrc/k_wave.hip", "paper_1608_05794_amd/csrc/kinetics.h",
                 "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h",
                 "paper_1608_05794_amd/csrc/mech.hip"],
-    "sha256": "0444d75f90944896969440a3d34f7d9e0af1ed11533442e74b531d8871c3ef8c",
+    "sha256": "7c78cc2891a2d95a0ce21f96f8ee9e5b13df6d8245c6f22a2c0ecade6ffc709b",
     "args": {"mech": "M53", "reactors": 131072, "t_end": 1e-3, "kernel": "wave", "precision": "fp64",
              "launch_steps": 2000},
-    "fetch_kib_per_launch": 687536.66, "fetch_factor": 1048576.0 / 524302.27,
-    "write_kib_per_launch": 370288869.13, "write_factor": 1.0,
+    "fetch_kib_per_launch": 176606.35, "fetch_factor": 1048576.0 / 524302.56,
+    "write_kib_per_launch": 393407601.11, "write_factor": 1.0,
 }
 TRANSCENDENTAL_FLOPS = 20           # FP64 operations charged per exp / log / log10 / exp10
 
@@ -269,18 +269,22 @@ def suite_batching(a):
         return dict(seconds=dt, reactors_per_s=n / dt, reactor_steps_per_s=float(s.sum().item()) / dt,
                     mean_steps=float(s.mean().item()), max_steps=float(s.max().item()), status_histogram=st, **kw)
 
-    # persistent workgroup kernel: host loop of bounded launches, then the graph-driven loop
-    _bounded_loop(ck, torch, g, y[:, :256], P[:256], te, 200, kernel="group")          # warm-up
-    r, dt, nl = _bounded_loop(ck, torch, g, y, P, te, 200, log=log, kernel="group")
-    out["persistent_host_loop"] = row(r, dt, launches=nl, launch_steps=200)
+    # persistent workgroup kernel (tile form): host loop of bounded launches, then the graph-driven
+    # loop; the half-row Gauss-Jordan form of the same kernel for comparison
+    _bounded_loop(ck, torch, g, y[:, :256], P[:256], te, 200, kernel="tile")           # warm-up
+    r, dt, nl = _bounded_loop(ck, torch, g, y, P, te, 200, log=log, kernel="tile")
+    out["persistent_host_loop"] = row(r, dt, launches=nl, launch_steps=200, kernel="tile")
     ref = r
     log(f"batching persistent host loop: {dt:.2f} s, {nl} launches")
-    gws = torch.empty(g.graph_workspace_bytes(n, kernel="group"), dtype=torch.uint8, device="cuda")
-    ck.integrate_graph(g, y[:, :256], P[:256], te, launch_steps=200, launches_per_graph=4, kernel="group",
+    _bounded_loop(ck, torch, g, y[:, :256], P[:256], te, 200, kernel="group")          # warm-up
+    r, dt, nl = _bounded_loop(ck, torch, g, y, P, te, 200, log=log, kernel="group")
+    out["persistent_half_row_host_loop"] = row(r, dt, launches=nl, launch_steps=200, kernel="group")
+    gws = torch.empty(g.graph_workspace_bytes(n, kernel="tile"), dtype=torch.uint8, device="cuda")
+    ck.integrate_graph(g, y[:, :256], P[:256], te, launch_steps=200, launches_per_graph=4, kernel="tile",
                        workspace=gws)                                                # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    gr = ck.integrate_graph(g, y, P, te, launch_steps=200, launches_per_graph=4, kernel="group", workspace=gws)
+    gr = ck.integrate_graph(g, y, P, te, launch_steps=200, launches_per_graph=4, kernel="tile", workspace=gws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     gr["steps"] = gr["n_accept"] + gr["n_reject"]
@@ -314,7 +318,7 @@ def suite_batching(a):
         log(f"autotune {mech}: {best}")
     # Eq. waste CDFs for widths 4..64 from a sample integrated further (to 1e-9 s)
     ys, Ps = _states(synth, torch, "M111", 2048, 1003)
-    r, dt = _timed_integrate(ck, torch, g, ys, Ps, 1e-9, kernel="group")
+    r, dt = _timed_integrate(ck, torch, g, ys, Ps, 1e-9, kernel="tile")
     st = (r["n_accept"] + r["n_reject"]).cpu().numpy()
     out["waste_sample"] = {
         "reactors": 2048, "t_end": 1e-9, "mean_steps": float(st.mean()), "max_steps": int(st.max()),
