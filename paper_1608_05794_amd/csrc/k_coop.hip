@@ -815,6 +815,17 @@ __device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, 
         for (int J = 0; J < TR; J++) m[i][J] = d4{0.0, 0.0, 0.0, 0.0};
     const bool keep = L.rows != nullptr && 3 * ((M.nrxn + G::T - 1) / G::T) <= H;
     double *cache = keep ? L.rows + opaque(tid) : nullptr;
+    // column sums sum_r H_r d wdot_r / dC_col accumulate in VX from the tiles; hr = H of the rows
+    // this lane holds (0 for the temperature row and padding)
+    if (tid < 128) L.VX[tid] = 0.0;
+    double hr[RW][4];
+#pragma unroll
+    for (int i = 0; i < RW; i++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int r = tile_row<F32L>(wv + 4 * i, g, v);
+            hr[i][v] = (r >= 1 && r <= ns) ? L.H[r - 1] : 0.0;
+        }
 #pragma unroll
     for (int w = 0; w < 2; w++) {
         const int c0 = w * H - 1;                   // window w: matrix columns [w H, w H + H)
@@ -842,12 +853,17 @@ __device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, 
                     const int r = tile_row<F32L>(I, g, v);
                     if (cin && r >= 1 && r <= ns) m[i][J][v] = L.JC[(r - 1) * L.ldj + (col - w * H)];
                 }
+                if (cin) {
+                    double part = 0.0;
+#pragma unroll
+                    for (int v = 0; v < 4; v++) part = fma(hr[i][v], m[i][J][v], part);
+                    atomicAdd(&L.VX[col], part);
+                }
             }
         }
-        if (valid && k + 1 >= w * H && k + 1 < w * H + H)
-            for (int r = 0; r < ns; r++) colH += L.H[r] * L.JC[r * L.ldj + (k + 1 - w * H)];
         __syncthreads();
     }
+    if (valid) colH = L.VX[k + 1];
     const double jrow = jcp + shfl_pair(jcp);
     if (half == 0 && rvalid) L.RJ[row] = jrow;
     __syncthreads();
@@ -963,8 +979,8 @@ __device__ __forceinline__ bool gj_invert_tiles(typename TileT<T>::V (&m)[TileGe
                     const T rp = TT::recip(TT::readlane(R1[c], src));
                     const T g0 = -R0[c] * rp, g1 = -R1[c] * rp;
 #pragma unroll
-                    for (int j = 0; j < 16; j++) {
-                        if (j == c) continue;
+                    for (int jj = 1; jj < 16; jj++) {
+                        const int j = (c + jj) & 15;      // the next pivot column first
                         const T pj = TT::readlane(R1[j], src);
                         R0[j] = fma(g0, pj, R0[j]);
                         const T u = fma(g1, pj, R1[j]);
@@ -977,8 +993,8 @@ __device__ __forceinline__ bool gj_invert_tiles(typename TileT<T>::V (&m)[TileGe
                     const T rp = TT::recip(TT::readlane(R0[c], src));
                     const T g0 = -R0[c] * rp, g1 = -R1[c] * rp;
 #pragma unroll
-                    for (int j = 0; j < 16; j++) {
-                        if (j == c) continue;
+                    for (int jj = 1; jj < 16; jj++) {
+                        const int j = (c + jj) & 15;      // the next pivot column first
                         const T pj = TT::readlane(R0[j], src);
                         const T u = fma(g0, pj, R0[j]);
                         R0[j] = piv ? pj * rp : u;
