@@ -16,6 +16,7 @@
 #include "launch.h"
 
 extern "C" __device__ unsigned long long __ockl_wfred_max_u64(unsigned long long);
+extern "C" __device__ unsigned __ockl_wfred_max_u32(unsigned);
 extern "C" __device__ double __ockl_wfred_add_f64(double);
 
 namespace ck {
@@ -507,11 +508,13 @@ __device__ __forceinline__ void lu_factor(double (&a)[NP], LU<NP> &f) {
     f.pivv = 0;
 #pragma unroll
     for (int k = 0; k < NP; k++) {
-        const unsigned long long key = done ? 0ull : (unsigned long long)__double_as_longlong(fabs(a[k]));
-        const unsigned long long mx = __ockl_wfred_max_u64(key);
+        // pivot search on the high word of |a| (ordered like |a|; candidates within a relative 2^-20
+        // of the largest may tie, and the first lane is taken)
+        const unsigned key = done ? 0u : unsigned(__double2hiint(fabs(a[k])));
+        const unsigned mx = __ockl_wfred_max_u32(key);
         const int p = __builtin_ctzll(__ballot(!done && key == mx));
         if (lane == k) f.pivv = p;
-        f.ok = f.ok && (mx != 0ull);
+        f.ok = f.ok && (mx != 0u);
         // 1 / pivot: hardware reciprocal estimate refined by two Newton-Raphson steps (within an
         // ulp; a shorter dependency chain than the correctly rounded division)
         const double piv = bcast(a[k], p);

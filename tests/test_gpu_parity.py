@@ -231,6 +231,31 @@ def test_edge_cases(ck, gmech, oracle_mech, method, kernel):
     assert weighted_error(res["y"], orc["y"]) <= 1e-9
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_tile_edge_cases(ck, gmech, oracle_mech, precision):
+    """Tile form (N = 112): an empty batch, a single reactor (one workgroup for one reactor, most of
+    the grid idle), a non-finite state among finite ones, the attempted-step cap and a step below the
+    h floor, each with the oracle's statuses."""
+    g, om = gmech("M111"), oracle_mech("M111")
+    y, P = synth.reactor_states(om.n_species, 5, "divergent", seed=1016)
+    te = 2e-12
+    kw = dict(precision=precision)
+    print(f"[tile edge cases {precision}]", flush=True)
+    empty = ck.integrate(g, dev(y[:, :0]), dev(P[:0]), te, kernel="tile", **kw)
+    assert empty["status"].numel() == 0
+    res, orc = _integrate_both(ck, g, om, y[:, :1], P[:1], te, "ros4", "tile", **kw)
+    assert np.array_equal(res["status"], orc["status"]) and res["status"][0] == 0
+    _report_and_check(f"tile one reactor {precision}", res, orc)
+    bad = y.copy()
+    bad[5, 2] = np.inf
+    res, orc = _integrate_both(ck, g, om, bad, P, te, "ros4", "tile", **kw)
+    assert res["status"][2] == 3 and np.array_equal(res["status"], orc["status"])
+    res, orc = _integrate_both(ck, g, om, y, P, 1e-6, "ros4", "tile", max_steps=9, **kw)
+    assert np.all(res["status"] == 1) and np.all(res["n_accept"] + res["n_reject"] == 9)
+    res, orc = _integrate_both(ck, g, om, y, P, 1e-6, "ros4", "tile", h0=1e-32, **kw)
+    assert np.all(res["status"] == 2) and np.array_equal(res["status"], orc["status"])
+
+
 @pytest.mark.parametrize("kernel", ["wave", "lane", "group"])
 def test_resume_and_batch_independence(ck, gmech, kernel):
     """(t, h, y) resume is bitwise; a reactor's result does not depend on its batch (Section 4: scalar and
