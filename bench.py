@@ -42,11 +42,11 @@ TRAFFIC_REF = {
     "sources": ["paper_1608_05794_amd/csrc/k_wave.hip", "paper_1608_05794_amd/csrc/kinetics.h",
                 "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h",
                 "paper_1608_05794_amd/csrc/mech.hip"],
-    "sha256": "7c78cc2891a2d95a0ce21f96f8ee9e5b13df6d8245c6f22a2c0ecade6ffc709b",
+    "sha256": "e5fce2a47b028273c833b0926bc6464492e5600f412b4ad811e437c154961d3f",
     "args": {"mech": "M53", "reactors": 131072, "t_end": 1e-3, "kernel": "wave", "precision": "fp64",
              "launch_steps": 2000},
-    "fetch_kib_per_launch": 176606.35, "fetch_factor": 1048576.0 / 524302.56,
-    "write_kib_per_launch": 393407601.11, "write_factor": 1.0,
+    "fetch_kib_per_launch": 10122678.30, "fetch_factor": 1048576.0 / 524302.31,
+    "write_kib_per_launch": 909188760.31, "write_factor": 1.0,
 }
 TRANSCENDENTAL_FLOPS = 20           # FP64 operations charged per exp / log / log10 / exp10
 
