@@ -439,6 +439,38 @@ def cpu_baseline_rate(path, y, P, t_end, n, threads, **kw):
             "mean_steps": float(np.mean(res["n_accept"] + res["n_reject"]))}
 
 
+def deep_vs_shallow(ck, torch, synth, n=32768, reps=5):
+    """Source term and analytic Jacobian evaluations per second at 13, 53 and 111 species, deep
+    vectorisation (one reactor per wavefront for N <= 64, per four-wavefront group above) against
+    shallow (one reactor per lane): median of `reps` launches on distinct seeded states, timed with
+    HIP events on the launch stream."""
+    res = {"reactors": n, "unit": "evaluations/s"}
+    for name, ns in (("M13", 13), ("M53", 53), ("M111", 111)):
+        g = ck.Mechanism(synth.mechanism_file(name))
+        y0, P0 = synth.reactor_states(ns, n, "mid", seed=1003)
+        y, P = torch.as_tensor(y0, device="cuda"), torch.as_tensor(P0, device="cuda")
+        row = {}
+        for op in ("rhs", "jacobian"):
+            for fam, kern in (("deep", "wave"), ("shallow", "lane")):
+                fn = (lambda: ck.rhs(g, y, P, kernel=kern)) if op == "rhs" else (lambda: ck.jac(g, y, P, kernel=kern))
+                fn()
+                times = []
+                for _ in range(reps):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    out = fn()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    times.append(e0.elapsed_time(e1) / 1e3)
+                    del out
+                row[f"{op}_{fam}"] = n / float(np.median(times))
+            row[f"{op}_deep_over_shallow"] = row[f"{op}_deep"] / row[f"{op}_shallow"]
+        print(f"methods deep vs shallow {name}: {row}", file=sys.stderr, flush=True)
+        res[name] = row
+        g.close()
+    return res
+
+
 def suite_methods(a):
     """The small configuration (13 species x 1024 reactors to 1e-4 s) with ROS4 and RKF45, a stiffness
     census of its initial states, its CPU baseline (the oracle on all host cores and on one); the rate
@@ -513,6 +545,7 @@ def suite_methods(a):
         print(f"methods jacobian {kind}: {dt:.2f} s", file=sys.stderr, flush=True)
     jac["analytic_speedup"] = jac["fd"]["seconds_median_of_3"] / jac["analytic"]["seconds_median_of_3"]
     out["jacobian"] = jac
+    out["deep_vs_shallow"] = deep_vs_shallow(ck, torch, synth)
     # CPU baseline on one core for the headline workload's states (ROS4 to 1e-3 s)
     y0, P0 = synth.reactor_states(53, 4, "mid", seed=1002)
     out["cpu_baseline_one_core_M53_1e-3"] = cpu_baseline_rate(path, y0, P0, 1e-3, 4, 1)
