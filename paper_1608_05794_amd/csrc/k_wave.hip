@@ -30,6 +30,11 @@ __device__ __forceinline__ int opaque(int v) {
     return v;
 }
 __device__ __forceinline__ int lane_fresh() { return opaque(__lane_id()); }
+// The same for a wave-uniform value, kept in a scalar register.
+__device__ __forceinline__ int opaque_s(int v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
 __device__ __forceinline__ double wsum(double v) { return __ockl_wfred_add_f64(v); }
 __device__ __forceinline__ double bcast(double v, int src) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -440,14 +445,21 @@ __device__ __forceinline__ void jac_rows_win(const DevMech &M, const Lds &L, dou
         if (w == 0) finish_rhs<1>(M, L, x, ff);
         // raw d wdot_k / dC_(c0+j) into column 1 + c0 + j of the row registers; the chain-rule
         // scalars of the row are applied once every window is in
+        // (every lane reads an in-range entry and keeps it under a bit mask, so that the reads
+        // are not split into one masked branch each; the column tests use a scalar copy of ns
+        // that the compiler cannot hoist out of the reactor loop, where the tests' results would
+        // occupy and spill scalar registers)
         const double *row = &L.JC[(valid ? k : 0) * L.ldj];
+        const int vkeep = opaque(valid ? -1 : 0);
+        const int nsw = opaque_s(ns);
 #pragma unroll
         for (int j = 0; j < WIN; j++) {
             if (1 + c0 + j >= NP) break;
-            const bool in = c0 + j < ns;
-            const double v = (valid && in) ? row[j] : 0.0;
+            const bool in = c0 + j < nsw;
+            const double e = row[j];
+            const double v = __hiloint2double(__double2hiint(e) & vkeep, __double2loint(e) & vkeep);
             if (in) jcc += v * L.C[c0 + j];
-            a[1 + c0 + j] = v;
+            a[1 + c0 + j] = in ? v : 0.0;
         }
         if (valid && k >= c0 && k < c0 + WIN)
             for (int r = 0; r < ns; r++) {
