@@ -42,11 +42,11 @@ TRAFFIC_REF = {
     "sources": ["paper_1608_05794_amd/csrc/k_wave.hip", "paper_1608_05794_amd/csrc/kinetics.h",
                 "paper_1608_05794_amd/csrc/ck_internal.h", "paper_1608_05794_amd/csrc/launch.h",
                 "paper_1608_05794_amd/csrc/mech.hip"],
-    "sha256": "e5fce2a47b028273c833b0926bc6464492e5600f412b4ad811e437c154961d3f",
+    "sha256": "45bf3512875cebbad468a548f6952454bb4ab27ef01445e2dea2656d3ee155d1",
     "args": {"mech": "M53", "reactors": 131072, "t_end": 1e-3, "kernel": "wave", "precision": "fp64",
              "launch_steps": 2000},
-    "fetch_kib_per_launch": 10122678.30, "fetch_factor": 1048576.0 / 524302.31,
-    "write_kib_per_launch": 909188760.31, "write_factor": 1.0,
+    "fetch_kib_per_launch": 7323296.37, "fetch_factor": 1048576.0 / 524302.31,
+    "write_kib_per_launch": 832079207.05, "write_factor": 1.0,
 }
 TRANSCENDENTAL_FLOPS = 20           # FP64 operations charged per exp / log / log10 / exp10
 

@@ -2,8 +2,8 @@
 (ck_integrate_ros4 with a library-owned workspace), through the C ABI: two calls in a row on each
 mechanism, the second with a smaller batch (the fixed device array keeps the previous call's
 contents).  Bitwise for the single-wavefront kernel (13 and 53 species); to the integration
-tolerance for the four-wavefront workgroup kernel (111 species, reaction sums ordered by LDS
-atomics across wavefronts)."""
+tolerance for the four-wavefront workgroup kernels, half-row and tile forms (111 species,
+reaction sums ordered by LDS atomics across wavefronts)."""
 import numpy as np
 import pytest
 import torch
@@ -15,7 +15,7 @@ from .parity_util import weighted_error
 pytestmark = pytest.mark.gpu
 
 CASES = [("M13", "small", (300, 77), 1e-6, "wave"), ("M53", "mid", (260, 65), 1e-7, "wave"),
-         ("M111", "divergent", (40, 9), 2e-10, "group")]
+         ("M111", "divergent", (40, 9), 2e-10, "group"), ("M111", "divergent", (40, 9), 2e-10, "tile")]
 
 
 @pytest.mark.parametrize("name,recipe,sizes,t_end,kernel", CASES)
