@@ -308,6 +308,32 @@ def suite_batching(a):
     out["speedup_graph_over_host_loop"] = (out["persistent_graph_loop"]["reactors_per_s"] /
                                            out["persistent_host_loop"]["reactors_per_s"])
 
+    # short launches (a serving-like loop of a few attempted steps per launch): the host loop
+    # synchronises and reads the statuses after every launch, the graph loop once per replay
+    ns_, te_s, ls, lpg = 4096, 1e-5, 8, 16
+    gs = ck.Mechanism(synth.mechanism_file("M13"))
+    ys, Ps = _states(synth, torch, "M13", ns_, 1001)
+    short = {"workload": f"M13 x {ns_} reactors (small states, seed 1001), ROS4 to {te_s:g} s, "
+                         f"{ls} attempted steps per launch, wavefront kernel"}
+    _bounded_loop(ck, torch, gs, ys[:, :256], Ps[:256], te_s, ls, kernel="wave")        # warm-up
+    r, dt, nl = _bounded_loop(ck, torch, gs, ys, Ps, te_s, ls, kernel="wave")
+    short["host_loop"] = dict(seconds=dt, reactors_per_s=ns_ / dt, launches=nl)
+    gws_s = torch.empty(gs.graph_workspace_bytes(ns_, kernel="wave"), dtype=torch.uint8, device="cuda")
+    ck.integrate_graph(gs, ys[:, :256], Ps[:256], te_s, launch_steps=ls, launches_per_graph=lpg, kernel="wave",
+                       workspace=gws_s)                                               # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gr = ck.integrate_graph(gs, ys, Ps, te_s, launch_steps=ls, launches_per_graph=lpg, kernel="wave", workspace=gws_s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    short["graph_loop"] = dict(seconds=dt, reactors_per_s=ns_ / dt, replays=gr["replays"], launches_per_graph=lpg)
+    short["statuses_equal"] = bool(torch.equal(gr["status"], r["status"]))
+    short["states_equal"] = bool(torch.equal(gr["y"], r["y"]))
+    short["speedup_graph_over_host_loop"] = short["host_loop"]["seconds"] / short["graph_loop"]["seconds"]
+    out["short_launches"] = short
+    log(f"batching short launches: host loop {short['host_loop']['seconds']:.3f} s ({nl} launches), graph loop "
+        f"{dt:.3f} s ({gr['replays']} replays)")
+
     # launch configuration chosen by the autotuner on a 16384-reactor sample of each workload
     for mech, seed in (("M53", 1002), ("M111", 1003)):
         gm = ck.Mechanism(synth.mechanism_file(mech))
