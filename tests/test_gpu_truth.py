@@ -15,8 +15,10 @@ required to be about as close to it as the oracle's own rtol 1e-8 result is:
 
 The samples are the headline workload (53 species, 1e-3 s, the benchmark's bounded launches of
 2000 attempted steps resuming from (t, h) with an explicit workspace), the 111-species
-half-hot / half-cold states with the four-wavefront group kernel, and the explicit RKF45 pair on
-the same states over a horizon it can cover.  A reactor's result does not depend on which other
+half-hot / half-cold states with the four-wavefront group kernels (half-row and tile forms), both
+in FP64 and with the FP32 factorisation refined in FP64 (the same bar: the refinement has to reach
+the FP64 solution's accuracy), and the explicit RKF45 pair on the same states over a horizon it
+can cover.  A reactor's result does not depend on which other
 reactors share the launch (tested in test_gpu_parity.py), so the sample runs alone.
 """
 import hashlib
@@ -35,11 +37,13 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 K = 10.0
 
-CASES = [  # golden case, method, kernel, attempted steps per bounded launch
-    ("m53_mid_1e-3", "ros4", "wave", 2000),
-    ("m111_divergent_2e-9", "ros4", "group", 200),
-    ("m111_divergent_2e-9", "ros4", "tile", 200),
-    ("m111_divergent_2e-12", "rkf45", "wave", 2000),
+CASES = [  # golden case, method, kernel, attempted steps per bounded launch, precision
+    ("m53_mid_1e-3", "ros4", "wave", 2000, "fp64"),
+    ("m53_mid_1e-3", "ros4", "wave", 2000, "fp32_refine"),
+    ("m111_divergent_2e-9", "ros4", "group", 200, "fp64"),
+    ("m111_divergent_2e-9", "ros4", "tile", 200, "fp64"),
+    ("m111_divergent_2e-9", "ros4", "tile", 200, "fp32_refine"),
+    ("m111_divergent_2e-12", "rkf45", "wave", 2000, "fp64"),
 ]
 
 
@@ -51,8 +55,8 @@ def _rel(a, ref):
     return eT, eY.max(axis=0)
 
 
-@pytest.mark.parametrize("case,method,kernel,launch_steps", CASES)
-def test_closer_to_reference_than_tolerance(mech_path, case, method, kernel, launch_steps):
+@pytest.mark.parametrize("case,method,kernel,launch_steps,precision", CASES)
+def test_closer_to_reference_than_tolerance(mech_path, case, method, kernel, launch_steps, precision):
     from paper_1608_05794_amd import ck
     with open(os.path.join(GOLDEN, f"truth_{case}.json")) as fh:
         gold = json.load(fh)
@@ -66,7 +70,7 @@ def test_closer_to_reference_than_tolerance(mech_path, case, method, kernel, lau
     ys, Ps = np.ascontiguousarray(y[:, idx]), np.ascontiguousarray(P[idx])
     ref = np.array(gold["y"]).T
     n, te = len(idx), gold["t_end"]
-    print(f"[truth {case}] {method} {kernel}: {n} reactors to {te:g} s", flush=True)
+    print(f"[truth {case}] {method} {kernel} {precision}: {n} reactors to {te:g} s", flush=True)
 
     # the library, in bounded launches resuming from (t, h), with an explicit workspace
     dev = torch.device("cuda", 0)
@@ -75,11 +79,11 @@ def test_closer_to_reference_than_tolerance(mech_path, case, method, kernel, lau
     ted = torch.full((n,), te, dtype=torch.float64, device=dev)
     t = torch.zeros(n, dtype=torch.float64, device=dev)
     h = torch.zeros(n, dtype=torch.float64, device=dev)
-    ws = torch.empty(g.workspace_bytes(n, kernel=kernel), dtype=torch.uint8, device=dev)
+    ws = torch.empty(g.workspace_bytes(n, kernel=kernel, precision=precision), dtype=torch.uint8, device=dev)
     steps = torch.zeros(n, dtype=torch.int64, device=dev)
     for launch in range(1000):
         r = ck.integrate(g, yd, Pd, ted, method=method, t=t, h=h, workspace=ws, inplace=True, kernel=kernel,
-                         max_steps=launch_steps)
+                         max_steps=launch_steps, precision=precision)
         steps += r["n_accept"] + r["n_reject"]
         left = int((r["status"] == 1).sum().item())
         print(f"  launch {launch + 1}: {left} reactors unfinished", flush=True)
