@@ -110,6 +110,10 @@ MECHS = {
     # test-only: N = 71 is not a multiple of 8 or 16, so the N > 64 kernels carry padding rows
     # and columns (and the tile form has five tile rows: uneven ownership over four wavefronts)
     "M70": dict(nsp=70, nrxn=420, n_tb=36, n_troe=24, elements="CHON", max_atoms=8, max_c=3, seed=70),
+    # test-only: the largest sizes of each kernel family, N = 64 (one reactor per wavefront, every
+    # lane a matrix row) and N = 128 (the four-wavefront workgroup kernels: eight tile rows)
+    "M63": dict(nsp=63, nrxn=380, n_tb=34, n_troe=26, elements="CHON", max_atoms=8, max_c=3, seed=63),
+    "M127": dict(nsp=127, nrxn=900, n_tb=64, n_troe=40, elements="CHON", max_atoms=9, max_c=3, seed=127),
 }
 
 

@@ -23,7 +23,8 @@ from .parity_util import jac_scaled_error, rhs_scale, state_rel_error, weighted_
 
 pytestmark = pytest.mark.gpu
 
-RECIPE = {"M13": "small", "M53": "mid", "M111": "divergent", "M70": "divergent", "M35X": "mid"}
+RECIPE = {"M13": "small", "M53": "mid", "M111": "divergent", "M70": "divergent", "M35X": "mid", "M63": "mid",
+          "M127": "divergent"}
 
 
 @pytest.fixture(scope="module")
@@ -453,3 +454,26 @@ def test_cv_rejected_where_unsupported(ck, gmech):
     y, P = synth.reactor_states(g111.n_species, 2, "divergent", seed=3)
     with pytest.raises(ck.CkError):
         ck.integrate(g111, dev(y), dev(P), 1e-9, reactor="cv")
+
+
+@pytest.mark.parametrize("name,kernel,n,te", [("M63", "wave", 24, 1e-7), ("M127", "tile", 12, 1e-9),
+                                             ("M127", "group", 12, 1e-9)])
+def test_largest_sizes(ck, gmech, oracle_mech, name, kernel, n, te):
+    """The largest state of each kernel family: N = 64 fills every lane of the wavefront kernel with
+    a matrix row (no padding column), N = 128 gives the workgroup kernels eight tile rows (two per
+    wavefront) and a 128-row Gauss-Jordan.  Source term, analytic Jacobian and ROS4 against the
+    oracle, in FP64 and (wavefront and tile forms) with the FP32 factorisation refined in FP64."""
+    g, om = gmech(name), oracle_mech(name)
+    assert om.N in (64, 128)
+    y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=303)
+    print(f"[largest {name} N={om.N}] {kernel}: {n} reactors to {te:g} s", flush=True)
+    f = ck.rhs(g, dev(y), dev(P), kernel="wave").cpu().numpy()
+    err = np.abs(f - om.rhs(y, P)) / rhs_scale(om, y, P)
+    J = ck.jac(g, dev(y), dev(P), kernel="wave").cpu().numpy().T.reshape(n, om.N, om.N)
+    ej = jac_scaled_error(J, om.jac(y, P), y)
+    print(f"  rhs scaled error {err.max():.3e}, jacobian scaled error {ej:.3e}", flush=True)
+    assert err.max() <= 1e-12 and ej <= 1e-10
+    for prec in (("fp64",) if kernel == "group" else ("fp64", "fp32_refine")):
+        res, orc = _integrate_both(ck, g, om, y, P, te, "ros4", kernel, precision=prec)
+        assert np.all(res["status"] == 0) and np.all(orc["status"] == 0)
+        _report_and_check(f"largest {name} {kernel} {prec}", res, orc)
