@@ -462,7 +462,8 @@ def test_largest_sizes(ck, gmech, oracle_mech, name, kernel, n, te):
     """The largest state of each kernel family: N = 64 fills every lane of the wavefront kernel with
     a matrix row (no padding column), N = 128 gives the workgroup kernels eight tile rows (two per
     wavefront) and a 128-row Gauss-Jordan.  Source term, analytic Jacobian and ROS4 against the
-    oracle, in FP64 and (wavefront and tile forms) with the FP32 factorisation refined in FP64."""
+    oracle, in FP64 and (wavefront and tile forms) with the FP32 factorisation refined in FP64;
+    RKF45 (one reactor per wavefront at both sizes) over a short horizon."""
     g, om = gmech(name), oracle_mech(name)
     assert om.N in (64, 128)
     y, P = synth.reactor_states(om.n_species, n, RECIPE[name], seed=303)
@@ -477,3 +478,8 @@ def test_largest_sizes(ck, gmech, oracle_mech, name, kernel, n, te):
         res, orc = _integrate_both(ck, g, om, y, P, te, "ros4", kernel, precision=prec)
         assert np.all(res["status"] == 0) and np.all(orc["status"] == 0)
         _report_and_check(f"largest {name} {kernel} {prec}", res, orc)
+    if kernel != "group":
+        # the explicit pair on the same states, over a horizon its stability bound allows
+        res, orc = _integrate_both(ck, g, om, y, P, 1e-12 if om.N == 64 else 1e-14, "rkf45", "wave")
+        assert np.all(res["status"] == 0) and np.all(orc["status"] == 0)
+        _report_and_check(f"largest {name} rkf45", res, orc)
