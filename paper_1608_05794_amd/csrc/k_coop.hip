@@ -753,6 +753,13 @@ struct TileGeom {
     static constexpr int UBLD = NP;               // row stride of the pivot-row buffer
     // scratch carved from the JC region: panel buffers [2][16][PLD] and pivot rows [16][UBLD]
     static constexpr size_t kScratch = size_t(2) * 16 * PLD + size_t(16) * UBLD;
+    // Tile row held in slot i by wavefront w (TR when none).  Up to seven tile rows, wavefront 0
+    // (which also eliminates the panels) holds only row 0 and the others rows w and w + 3, so its
+    // share of the updates is the smaller one; eight tile rows go two to each wavefront.
+    static constexpr int STRIDE = TR <= 7 ? 3 : 4;
+    __device__ static __forceinline__ int tile_of(int w, int i) {
+        return (TR <= 7 && w == 0 && i > 0) ? TR : w + STRIDE * i;
+    }
 };
 
 // Orders this wavefront's LDS accesses around an exchange between its own lanes (LDS operations
@@ -823,7 +830,7 @@ __device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, 
     for (int i = 0; i < RW; i++)
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            const int r = tile_row<F32L>(wv + 4 * i, g, v);
+            const int r = tile_row<F32L>(TileGeom<NP>::tile_of(wv, i), g, v);
             hr[i][v] = (r >= 1 && r <= ns) ? L.H[r - 1] : 0.0;
         }
 #pragma unroll
@@ -841,7 +848,7 @@ __device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, 
         // raw window entries d wdot_(r-1) / dC_(col-1) into this wavefront's tiles
 #pragma unroll
         for (int i = 0; i < RW; i++) {
-            const int I = wv + 4 * i;
+            const int I = TileGeom<NP>::tile_of(wv, i);
             if (I >= TR) break;
 #pragma unroll
             for (int J = 0; J < TR; J++) {
@@ -901,7 +908,7 @@ __device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, 
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < RW; i++) {
-        const int I = wv + 4 * i;
+        const int I = TileGeom<NP>::tile_of(wv, i);
         if (I >= TR) break;
 #pragma unroll
         for (int v = 0; v < 4; v++) {
@@ -921,14 +928,71 @@ __device__ __forceinline__ void iteration_tiles(const DevMech &M, const Lds &L, 
     __syncthreads();
 }
 
+// Rank-16 update of tile columns J0 <= J < J1 with eliminated panel p: A = the panel rows of this
+// wavefront's tile rows (PNL, column-major), B = the panel's pivot rows (UB), on the matrix cores.
+template <int J0, int J1, int NP, class T>
+__device__ __forceinline__ void tile_update(typename TileT<T>::V (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR],
+                                            const T *PNL, const T *UB, int p, int wv, int g, int c16) {
+    using TG = TileGeom<NP>;
+    constexpr int TR = TG::TR, RW = TG::RW, PLD = TG::PLD, UBLD = TG::UBLD;
+#pragma unroll
+    for (int i = 0; i < RW; i++) {
+        const int I = TG::tile_of(wv, i);
+        if (I >= TR) break;
+        T a[4];
+#pragma unroll
+        for (int s = 0; s < 4; s++) a[s] = PNL[(4 * s + g) * PLD + 16 * I + c16];
+#pragma unroll
+        for (int J = J0; J < J1; J++) {
+            const int gJ = p + J < TR ? p + J : p + J - TR;
+#pragma unroll
+            for (int s = 0; s < 4; s++) {
+                const T b = UB[(4 * s + g) * UBLD + 16 * gJ + c16];
+                m[i][J] = TileT<T>::mfma(a[s], b, m[i][J]);
+            }
+        }
+    }
+}
+
+// Tile column c of this wavefront's tile rows into an LDS panel buffer, column-major:
+// PNL[col PLD + r] = A[r][16 c + col].
+template <int NP, class T>
+__device__ __forceinline__ void store_panel(const typename TileT<T>::V (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR],
+                                            int c, T *PNL, int wv, int g, int c16) {
+    using TG = TileGeom<NP>;
+#pragma unroll
+    for (int i = 0; i < TG::RW; i++) {
+        const int I = TG::tile_of(wv, i);
+        if (I >= TG::TR) break;
+#pragma unroll
+        for (int v = 0; v < 4; v++) PNL[c16 * TG::PLD + tile_row<TileT<T>::F32L>(I, g, v)] = m[i][c][v];
+    }
+}
+
+// Tile columns rotate by one: the next panel becomes column 0.
+template <int NP, class V>
+__device__ __forceinline__ void rotate_tiles(V (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR]) {
+#pragma unroll
+    for (int i = 0; i < TileGeom<NP>::RW; i++) {
+        const V t0 = m[i][0];
+#pragma unroll
+        for (int J = 0; J + 1 < TileGeom<NP>::TR; J++) m[i][J] = m[i][J + 1];
+        m[i][TileGeom<NP>::TR - 1] = t0;
+    }
+}
+
 // Blocked Gauss-Jordan inverse in place on the tiles.  On return L.ORD[r] is the pivot order of
 // row r: tile entry (r, j) = Minv[ORD[r]][p_j], p_j the row that was pivot j.
+//
+// Panels of 16 columns with look-ahead: once panel p is eliminated and its pivot rows are in UB,
+// every wavefront first applies it to tile column 1 (the next panel) and stores that column, then
+// wavefront 0 eliminates panel p + 1 while the others apply panel p to the remaining columns;
+// wavefront 0 holds the fewest tile rows, so its own remaining updates are the shortest.
 template <int NP, class T = double>
 __device__ __forceinline__ bool gj_invert_tiles(typename TileT<T>::V (&m)[TileGeom<NP>::RW][TileGeom<NP>::TR],
                                                 const Lds &L) {
     using TG = TileGeom<NP>;
     using TT = TileT<T>;
-    using V = typename TT::V;
     constexpr bool F32L = TT::F32L;
     constexpr int TR = TG::TR, RW = TG::RW, PLD = TG::PLD, UBLD = TG::UBLD;
     using G = Grp<4>;
@@ -938,22 +1002,16 @@ __device__ __forceinline__ bool gj_invert_tiles(typename TileT<T>::V (&m)[TileGe
     if (tid < 128) L.ORD[tid] = NP;
     unsigned pmask = 0;          // wavefront 0: bit 0 (1) set once row l (l + 64) has been a pivot
     bool ok = true;
+    // panel 0 (tile column 0) into the first panel buffer
+    store_panel<NP, T>(m, 0, JCT, wv, g, c16);
+    __syncthreads();
     for (int p = 0; p < TR; p++) {
         T *const PNL = JCT + (p & 1) * 16 * PLD;
-        // (1) the panel (tile column 0: the tile columns rotate by one per panel) into LDS,
-        //     column-major: PNL[c PLD + r] = A[r][16 p + c]
-#pragma unroll
-        for (int i = 0; i < RW; i++) {
-            const int I = wv + 4 * i;
-            if (I >= TR) break;
-#pragma unroll
-            for (int v = 0; v < 4; v++) PNL[c16 * PLD + tile_row<F32L>(I, g, v)] = m[i][0][v];
-        }
-        __syncthreads();
-        // (2) wavefront 0 eliminates the panel with one panel row per lane (rows l and l + 64): the
+        // (1) wavefront 0 eliminates panel p with one panel row per lane (rows l and l + 64): the
         //     pivot search is a wavefront reduction, the pivot row reaches every lane by lane reads
         //     (scalar operands of the updates), and the pivot reciprocal comes from the hardware
-        //     estimate refined by Newton steps
+        //     estimate refined by Newton steps.  Meanwhile every wavefront finishes panel p - 1 on
+        //     tile columns 2.. (column 1 of panel p - 1 was this panel) and rotates its columns.
         if (wv == 0) {
             const bool has1 = ln + 64 < NP;
             T R0[16], R1[16];
@@ -1012,12 +1070,16 @@ __device__ __forceinline__ bool gj_invert_tiles(typename TileT<T>::V (&m)[TileGe
                 if (has1) PNL[c * PLD + ln + 64] = R1[c];
             }
         }
+        if (p > 0) {
+            tile_update<2, TR, NP, T>(m, JCT + ((p - 1) & 1) * 16 * PLD, UB, p - 1, wv, g, c16);
+            rotate_tiles<NP>(m);
+        }
         __syncthreads();
-        // (3) the eliminated panel into tile column 0; the pivot rows' entries of the other
+        // (2) the eliminated panel into tile column 0; the pivot rows' entries of the other
         //     columns into UB (as U[order within the panel][column]) and zeroed in the tiles
 #pragma unroll
         for (int i = 0; i < RW; i++) {
-            const int I = wv + 4 * i;
+            const int I = TileGeom<NP>::tile_of(wv, i);
             if (I >= TR) break;
 #pragma unroll
             for (int v = 0; v < 4; v++) {
@@ -1035,33 +1097,17 @@ __device__ __forceinline__ bool gj_invert_tiles(typename TileT<T>::V (&m)[TileGe
             }
         }
         __syncthreads();
-        // (4) rank-16 update of the other tile columns on the matrix cores
-#pragma unroll
-        for (int i = 0; i < RW; i++) {
-            const int I = wv + 4 * i;
-            if (I >= TR) break;
-            T a[4];
-#pragma unroll
-            for (int s = 0; s < 4; s++) a[s] = PNL[(4 * s + g) * PLD + 16 * I + c16];
-#pragma unroll
-            for (int J = 1; J < TR; J++) {
-                const int gJ = p + J < TR ? p + J : p + J - TR;
-#pragma unroll
-                for (int s = 0; s < 4; s++) {
-                    const T b = UB[(4 * s + g) * UBLD + 16 * gJ + c16];
-                    m[i][J] = TT::mfma(a[s], b, m[i][J]);
-                }
-            }
-        }
-        // (5) rotate the tile columns: the next panel becomes column 0
-#pragma unroll
-        for (int i = 0; i < RW; i++) {
-            const V t0 = m[i][0];
-#pragma unroll
-            for (int J = 0; J + 1 < TR; J++) m[i][J] = m[i][J + 1];
-            m[i][TR - 1] = t0;
+        // (3) look-ahead: panel p applied to tile column 1 (the next panel), which is then stored
+        //     for its elimination
+        if (p + 1 < TR) {
+            tile_update<1, 2, NP, T>(m, PNL, UB, p, wv, g, c16);
+            store_panel<NP, T>(m, 1, JCT + ((p + 1) & 1) * 16 * PLD, wv, g, c16);
+            __syncthreads();
         }
     }
+    // the last panel on every other tile column
+    tile_update<1, TR, NP, T>(m, JCT + ((TR - 1) & 1) * 16 * PLD, UB, TR - 1, wv, g, c16);
+    rotate_tiles<NP>(m);
     __syncthreads();
     return ok;
 }
@@ -1081,7 +1127,7 @@ __device__ __forceinline__ double gj_apply_tiles(const typename TileT<T>::V (&m)
     for (int J = 0; J < TR; J++) bs[J] = T(L.BS[16 * J + c16]);
 #pragma unroll
     for (int i = 0; i < RW; i++) {
-        if (wv + 4 * i >= TR) break;
+        if (TileGeom<NP>::tile_of(wv, i) >= TR) break;
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             T z = T(0);
@@ -1111,7 +1157,7 @@ __device__ __forceinline__ double resid_tiles(const d4 (&m)[TileGeom<NP>::RW][Ti
     for (int J = 0; J < TR; J++) xs[J] = L.VX[16 * J + c16];
 #pragma unroll
     for (int i = 0; i < RW; i++) {
-        const int I = wv + 4 * i;
+        const int I = TileGeom<NP>::tile_of(wv, i);
         if (I >= TR) break;
 #pragma unroll
         for (int v = 0; v < 4; v++) {
@@ -1189,7 +1235,7 @@ struct Ros4CoopTile {
             for (int i = 0; i < RW; i++)
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
-                    const int I = wv + 4 * i;
+                    const int I = TileGeom<NP>::tile_of(wv, i);
                     ordr[i][v] = I < TR ? L.ORD[tile_row(I, g, v)] : NP;
                 }
         }
@@ -1238,7 +1284,7 @@ struct Ros4CoopTile32 {
             for (int i = 0; i < RW; i++)
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
-                    const int I = wv + 4 * i;
+                    const int I = TileGeom<NP>::tile_of(wv, i);
                     ordr[i][v] = I < TR ? L.ORD[tile_row<true>(I, g, v)] : NP;
                 }
         }
