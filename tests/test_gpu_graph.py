@@ -32,7 +32,7 @@ def _host_loop(ck, g, y, p, t_end, method, launch_steps, launches, **opts):
 
 @pytest.mark.parametrize("name,method,n,t_end,ls,K", [("M53", "ros4", 200, 1e-7, 37, 3),
                                                       ("M13", "ros4", 300, 1e-6, 25, 4),
-                                                      ("M13", "rkf45", 150, 1e-9, 40, 2)])
+                                                      ("M13", "rkf45", 150, 1e-10, 40, 2)])
 def test_graph_equals_host_loop_at_every_replay(mech_path, name, method, n, t_end, ls, K):
     from paper_1608_05794_amd import ck
     g = ck.Mechanism(mech_path(name))
