@@ -161,10 +161,15 @@ class Mechanism:
 def rhs(mech, y, p, out=None, kernel=None, stream=None, reactor="cp"):
     """dy/dt for every reactor (ck_rhs_eval / ck_rhs_eval_ex); y [N, n] float64, p [n]: pressures (Pa)
     for reactor="cp", densities (kg/m^3) for "cv"."""
-    ld = _state(y, mech.N)
+    _state(y, mech.N)
     n = y.shape[1]
     _vec(p, n, y.device, "p")
-    out = torch.empty_like(y) if out is None else out
+    if out is None:
+        # the library writes out[i ld + r] with the state's leading dimension: pass a compact state
+        # so that a fresh compact output matches it
+        y = y.contiguous()
+        out = torch.empty_like(y)
+    ld = _state(y, mech.N)
     if out.dtype != torch.float64 or out.device != y.device or out.shape != y.shape or \
             out.stride(0) != ld or out.stride(1) != 1:
         raise CkError("output must be a float64 tensor with the state's shape, device and strides")

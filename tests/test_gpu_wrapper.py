@@ -35,6 +35,10 @@ def test_sliced_state_views(mech_path):
     Jb = ck.jac(g, before[:, 3:7].contiguous(), P[3:7])
     fa = ck.rhs(g, wide[:, 3:7].contiguous(), P[3:7])
     fb = ck.rhs(g, before[:, 3:7].contiguous(), P[3:7])
+    fc = ck.rhs(g, wide[:, 3:7], P[3:7])                     # a strided view without an output
+    fd = torch.zeros_like(wide)
+    ck.rhs(g, wide, P, out=fd)                               # an output with the state's strides
     torch.cuda.synchronize()
     assert Ja.shape == (g.N * g.N, 4) and torch.equal(Ja, Jb) and torch.equal(fa, fb)
+    assert fc.shape == (g.N, 4) and torch.equal(fc, fb) and torch.equal(fd[:, 3:7], fb)
     assert np.all(a["status"].cpu().numpy() == 0)
