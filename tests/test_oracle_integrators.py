@@ -253,3 +253,35 @@ def test_golden_stability_values_are_reproducible():
     from fractions import Fraction as Fr
     assert sol == [Fr(1), Fr(1), Fr(1, 2), Fr(1, 6), Fr(1, 24), Fr(1, 104)]
     assert err == [0, 0, 0, 0, 0, Fr(-1, 780), Fr(1, 2080)]
+
+
+@pytest.mark.parametrize("method", ["ros4", "rkf45"])
+def test_controller_closed_forms(method):
+    """Closed forms of the driver (Algorithm 1) under its stated controller: Hairer-Norsett-Wanner
+    starting step, step factor bounded to [0.2, 5], a step clipped onto t_end.
+
+    With a zero right-hand side the starting step takes the published fallback branch: both
+    derivative norms vanish, so h0 = 1e-6 and the second estimate is max(1e-6, 1e-3 h0) = 1e-6.
+    The error estimate is then 0 at every step, so each accepted step grows h by the upper bound
+    5: steps 1e-6 * 5^k, and the run ends after the first m with 1e-6 (5^m - 1) / 4 >= t_end,
+    the last step clipped, with no rejection.  On y' = -y, a step so small that its error is
+    negligible grows h by exactly 5, and one with an error estimate many orders above the
+    tolerance shrinks it by exactly the lower bound 0.2."""
+    A0 = np.zeros((2, 2))
+    y0 = np.array([1.0, 2.0])
+    for t_end, h0 in ((1e-3, 0.0), (1e-5, 0.0), (3e-2, 0.0), (1e-3, 1e-5), (2e-4, 3e-7)):
+        r = O.integrate_linear(A0, y0, t_end, method, h0=h0)
+        first = h0 if h0 > 0 else 1e-6
+        m = math.ceil(math.log(4.0 * t_end / first + 1.0, 5.0))
+        assert r["status"] == 0 and r["n_reject"] == 0 and r["n_accept"] == m, (t_end, h0, r)
+        assert r["t"] == t_end and np.array_equal(r["y"], y0)
+    # one accepted step of a zero error: h grows by 5
+    r = O.integrate_linear(A0, y0, 1.0, method, h0=1e-5, max_steps=1)
+    assert r["status"] == 1 and r["n_accept"] == 1 and r["h"] == 5.0 * 1e-5
+    A = np.array([[-1.0]])
+    # error estimate ~ h^5 / 1e-3, far below 1: the growth is capped at 5
+    r = O.integrate_linear(A, [1.0], 1.0, method, h0=1e-6, rtol=1e-3, atol=1e-3, max_steps=1)
+    assert r["status"] == 1 and r["n_accept"] == 1 and r["h"] == 5.0 * 1e-6
+    # error estimate ~ 1e-3 / 1e-14: rejected, and the shrink is bounded below by 0.2
+    r = O.integrate_linear(A, [1.0], 1.0, method, h0=0.5, rtol=1e-14, atol=1e-14, max_steps=1)
+    assert r["status"] == 1 and r["n_reject"] == 1 and r["h"] == 0.2 * 0.5 and r["t"] == 0.0
