@@ -40,12 +40,12 @@
  *     EstimateH0 and AdjustStepSize are not given in the paper; the choices
  *     (Hairer--Norsett--Wanner starting step, safety 0.9, factor bounds
  *     [0.2, 5]; (t, h, y) is the whole controller state) are a fixed specification
- *     shared with the GPU library.  Closed forms pin the starting step's
- *     fallback result (1e-6 for a zero right-hand side), the factor bounds
- *     (5 on acceptance, 0.2 on rejection), clipping and termination; parity
- *     unpinned for the factor between the bounds (0.9 err^(-1/q)) and the
- *     starting step's main branch, where step counts are "oracle equals GPU
- *     under the same specification" only.
+ *     shared with the GPU library.  Closed forms pin the starting step (its
+ *     fallback for a zero right-hand side and its main branch on a stiff
+ *     scalar problem), the factor bounds (5 on acceptance, 0.2 on rejection),
+ *     clipping and termination; parity unpinned for the factor between the
+ *     bounds (0.9 err^(-1/q)), where step counts are "oracle equals GPU under
+ *     the same specification" only.
  *   - Section 5.2: one reactor per OpenMP task, schedule(dynamic,1).
  *
  * Units: SI throughout (K, Pa, kg/mol, mol/m^3, J/mol, s).

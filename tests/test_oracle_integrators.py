@@ -266,7 +266,8 @@ def test_controller_closed_forms(method):
     5: steps 1e-6 * 5^k, and the run ends after the first m with 1e-6 (5^m - 1) / 4 >= t_end,
     the last step clipped, with no rejection.  On y' = -y, a step so small that its error is
     negligible grows h by exactly 5, and one with an error estimate many orders above the
-    tolerance shrinks it by exactly the lower bound 0.2."""
+    tolerance shrinks it by exactly the lower bound 0.2.  On a stiff scalar problem with an
+    absolute tolerance of zero the starting step's main branch has a closed form as well."""
     A0 = np.zeros((2, 2))
     y0 = np.array([1.0, 2.0])
     for t_end, h0 in ((1e-3, 0.0), (1e-5, 0.0), (3e-2, 0.0), (1e-3, 1e-5), (2e-4, 3e-7)):
@@ -285,3 +286,12 @@ def test_controller_closed_forms(method):
     # error estimate ~ 1e-3 / 1e-14: rejected, and the shrink is bounded below by 0.2
     r = O.integrate_linear(A, [1.0], 1.0, method, h0=0.5, rtol=1e-14, atol=1e-14, max_steps=1)
     assert r["status"] == 1 and r["n_reject"] == 1 and r["h"] == 0.2 * 0.5 and r["t"] == 0.0
+    # starting step's main branch on y' = lam y, y0 = 1, atol = 0 (error weight rtol): the published
+    # algorithm's norms are d0 = 1/rtol, d1 = |lam|/rtol and d2 = lam^2/rtol, so h0 = 0.01/|lam| and
+    # the start is min(100 h0, (0.01 rtol / lam^2)^(1/5)); at rtol 1e-14 that first step (|h lam| >=
+    # 0.15) is rejected with the 0.2 bound, which makes the start observable as h / 0.2
+    rtol = 1e-14
+    for lam in (-1e6, -1e4, 1e5):       # the 100 h0 cap; the fifth-root estimate (twice)
+        r = O.integrate_linear(np.array([[lam]]), [1.0], 1.0, method, rtol=rtol, atol=0.0, max_steps=1)
+        start = min(1.0 / abs(lam), (0.01 * rtol / lam ** 2) ** 0.2)
+        assert r["n_reject"] == 1 and math.isclose(r["h"], 0.2 * start, rel_tol=1e-12), (lam, r["h"], start)
