@@ -43,9 +43,9 @@
  *     shared with the GPU library.  Closed forms pin the starting step (its
  *     fallback for a zero right-hand side and its main branch on a stiff
  *     scalar problem), the factor bounds (5 on acceptance, 0.2 on rejection),
- *     clipping and termination; parity unpinned for the factor between the
- *     bounds (0.9 err^(-1/q)), where step counts are "oracle equals GPU under
- *     the same specification" only.
+ *     the factor between them (exponent 1/q from a problem whose estimate is
+ *     exactly C h^q; the safety factor 0.9 from the pair's error polynomial),
+ *     clipping and termination.
  *   - Section 5.2: one reactor per OpenMP task, schedule(dynamic,1).
  *
  * Units: SI throughout (K, Pa, kg/mol, mol/m^3, J/mol, s).

@@ -295,3 +295,31 @@ def test_controller_closed_forms(method):
         r = O.integrate_linear(np.array([[lam]]), [1.0], 1.0, method, rtol=rtol, atol=0.0, max_steps=1)
         start = min(1.0 / abs(lam), (0.01 * rtol / lam ** 2) ** 0.2)
         assert r["n_reject"] == 1 and math.isclose(r["h"], 0.2 * start, rel_tol=1e-12), (lam, r["h"], start)
+
+
+@pytest.mark.parametrize("method,q,h0s", [("ros4", 4, (0.1, 0.2, 0.4, 0.7)), ("rkf45", 5, (0.3, 0.5, 0.8, 1.2))])
+def test_step_factor_exponent_matches_estimate_order(method, q, h0s):
+    """The factor between the bounds, 0.9 err^(-1/q), uses the order q of the error estimate (4 for
+    ROS4, 5 for RKF45).  On y' = S y with S the (q+1) x (q+1) shift matrix (S^(q+1) = 0) and a
+    purely absolute tolerance, the estimate of one step is exactly C h^q (every lower power of hS
+    cancels between the method and its embedded partner, every higher one vanishes), so with the
+    matching exponent the next step size 0.9 (C h^q)^(-1/q) h does not depend on h, accepted or
+    rejected.  Any other exponent makes it a power of h."""
+    S = np.diag(np.ones(q), 1)
+    y0 = np.zeros(q + 1)
+    y0[-1] = 1.0
+    nxt = []
+    for h0 in h0s:
+        r = O.integrate_linear(S, y0, 10.0, method, h0=h0, rtol=0.0, atol=1e-3, max_steps=1)
+        assert r["n_accept"] + r["n_reject"] == 1
+        nxt.append(r["h"])
+    # the largest start is rejected (estimate above 1), the others accepted
+    assert r["n_reject"] == 1
+    assert np.allclose(nxt, nxt[0], rtol=1e-12, atol=0.0), nxt
+    assert 0.2 * h0s[-1] < nxt[0] < 5.0 * h0s[0]      # inside both bounds for every start
+    if method == "rkf45":
+        # the pair's estimate on y' = lam y is (e5 z^5 + e6 z^6) y0 (Appendix B, stored golden values),
+        # so here C = |e5| / (atol sqrt(q + 1)) (the RMS norm over q + 1 components of which one is
+        # nonzero) and the step size settles at 0.9 C^(-1/5): this pins the safety factor 0.9
+        C = abs(GOLD["rkf45_err_poly"]["coeffs"][5]) / (1e-3 * math.sqrt(q + 1))
+        assert nxt[0] == pytest.approx(0.9 * C ** (-1.0 / q), rel=1e-12)
