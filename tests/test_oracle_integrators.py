@@ -323,3 +323,23 @@ def test_step_factor_exponent_matches_estimate_order(method, q, h0s):
         # nonzero) and the step size settles at 0.9 C^(-1/5): this pins the safety factor 0.9
         C = abs(GOLD["rkf45_err_poly"]["coeffs"][5]) / (1e-3 * math.sqrt(q + 1))
         assert nxt[0] == pytest.approx(0.9 * C ** (-1.0 / q), rel=1e-12)
+
+
+def test_error_weights_use_the_larger_of_old_and_new_state():
+    """The error weights are atol + rtol max(|y|, |y_new|) per component.  On y' = S y (S the 6 x 6
+    shift matrix, y0 the last unit vector) the RKF45 estimate lives in the first component, where
+    y0 is 0 and the new state is r5 h^5 (r5 = 1/104, the z^5 coefficient of the fourth-order
+    weights' polynomial) while the estimate is e5 h^5 (e5 = -1/780; Appendix B, stored golden
+    values).  With atol = 0 the error is |e5| / (rtol r5 sqrt(6)) for every h, and the step grows by
+    0.9 times its -1/5 power; weights from y0 alone would divide by zero there."""
+    q = 5
+    S = np.diag(np.ones(q), 1)
+    y0 = np.zeros(q + 1)
+    y0[-1] = 1.0
+    e5, r5 = abs(GOLD["rkf45_err_poly"]["coeffs"][5]), GOLD["rkf45_b_poly"]["coeffs"][5]
+    for rtol in (1.0, 0.1):
+        err = e5 / (rtol * r5 * math.sqrt(q + 1))
+        for h0 in (0.01, 0.3):
+            r = O.integrate_linear(S, y0, 10.0, "rkf45", h0=h0, rtol=rtol, atol=0.0, max_steps=1)
+            assert r["n_accept"] == 1
+            assert r["h"] / h0 == pytest.approx(0.9 * err ** (-1.0 / q), rel=1e-12)
