@@ -48,3 +48,37 @@ def test_fd_ros4_integration_agrees_with_analytic(oracle_mech):
     assert np.all(ra["status"] == 0) and np.all(rf["status"] == 0)
     w = np.abs(rf["y"] - ra["y"]) / (np.abs(ra["y"]) + 1e-12 / 1e-8)
     assert w.max() <= 1e-6
+
+
+def test_fd_increments_follow_the_stated_rule(oracle_mech):
+    """The forward difference of column j has error inc_j / 2 * d2f/dy_j2 + O(inc_j^2), so the
+    increment the oracle used can be read back from its FD Jacobian: inc_j ~ 2 (J_fd - J)_ij / H_ij,
+    with J the analytic Jacobian (pinned against central differences) and H_ij = dJ_ij/dy_j from
+    central differences of J, in the row where truncation dominates rounding most.  The stated rule
+    (CVODE's dense difference quotient) is inc_j = max(sqrt(eps) |y_j|, min_inc (rtol |y_j| + atol)),
+    min_inc = 1000 |h| eps N ||f||_w.  On these states and step sizes the min_inc branch holds for
+    every column and the read-back agrees to a few per cent; a dropped or changed factor (1000, N,
+    eps for sqrt(eps), the RMS for a sum) moves it by 3.7x or more.  The sqrt(eps) |y_j| branch is
+    not read back: where it holds, rounding dominates the difference."""
+    eps = np.finfo(np.float64).eps
+    rtol, atol = 1e-8, 1e-12
+    for name, recipe, seed, h in (("M13", "small", 11, 1e-7), ("M13", "small", 12, 1e-7), ("M53", "mid", 11, 1e-5)):
+        m = oracle_mech(name)
+        y, P = synth.reactor_states(m.n_species, 1, recipe, seed=seed)
+        N = m.N
+        J = m.jac(y, P)[0]
+        f = m.rhs(y, P)[:, 0]
+        w = 1.0 / (rtol * np.abs(y[:, 0]) + atol)
+        min_inc = 1000.0 * h * eps * N * np.sqrt(np.mean((f * w) ** 2))
+        inc = np.maximum(np.sqrt(eps) * np.abs(y[:, 0]), min_inc / w)
+        Jf = m.jac_fd(y, P, h=h, rtol=rtol, atol=atol)[0]
+        got = np.empty(N)
+        for j in range(N):
+            d = 1e-4 * max(abs(y[j, 0]), 1e-6)
+            yp, ym = y.copy(), y.copy()
+            yp[j, 0] += d
+            ym[j, 0] -= d
+            H = (m.jac(yp, P)[0][:, j] - m.jac(ym, P)[0][:, j]) / (2.0 * d)
+            i = np.argmax(np.abs(H) * inc[j] ** 2 / (np.abs(f) + 1e-300))
+            got[j] = 2.0 * (Jf[i, j] - J[i, j]) / H[i]
+        assert np.all(np.abs(got / inc - 1.0) <= 0.05), (name, seed, np.round(got / inc, 3))
