@@ -163,11 +163,12 @@ class Mechanism:
 
 
 def integrate_linear(A, y0, t_end, method="ros4", rtol=1e-8, atol=1e-12, h0=0.0, h_fixed=0.0, max_steps=1_000_000,
-                     jacobian="analytic"):
+                     jacobian="analytic", t0=0.0):
+    """y' = A y from t0 to t_end.  Returns dict(y, t, h, status, n_accept, n_reject, nfev)."""
     A = np.ascontiguousarray(A, dtype=np.float64)
     N = A.shape[0]
     y = np.array(y0, dtype=np.float64)
-    t, h = C.c_double(0.0), C.c_double(0.0)
+    t, h = C.c_double(float(t0)), C.c_double(0.0)
     st, na, nr = C.c_int32(), C.c_int32(), C.c_int32()
     nfev = C.c_long()
     o = make_opts(rtol, atol, h0, h_fixed, max_steps, jacobian)

@@ -343,3 +343,17 @@ def test_error_weights_use_the_larger_of_old_and_new_state():
             r = O.integrate_linear(S, y0, 10.0, "rkf45", h0=h0, rtol=rtol, atol=0.0, max_steps=1)
             assert r["n_accept"] == 1
             assert r["h"] / h0 == pytest.approx(0.9 * err ** (-1.0 / q), rel=1e-12)
+
+
+@pytest.mark.parametrize("method", ["ros4", "rkf45"])
+def test_step_floor_is_relative_to_t(method):
+    """H_UNDERFLOW once the proposed step falls below max(1e-30 s, 16 eps |t|).  On y' = -1e14 y at
+    a tolerance of 1e-14 the first step (|h lam| ~ 1.7) is rejected with the 0.2 bound, so the
+    proposal is exactly 0.2 h0: just below 16 eps |t| it stops the run, just above it does not, and
+    at t = 0 only the absolute floor applies."""
+    A = np.array([[-1e14]])
+    for t0, h0, status in ((1.0, 1.7e-14, 2), (1.0, 1.8e-14, 1), (0.0, 1.7e-14, 1),
+                           (1e3, 1.7e-11, 2), (1e3, 1.8e-11, 1)):
+        assert (0.2 * h0 < 16 * np.finfo(np.float64).eps * t0) == (status == 2)
+        r = O.integrate_linear(A, [1.0], t0 + 1.0, method, rtol=1e-14, atol=1e-14, h0=h0, max_steps=1, t0=t0)
+        assert r["n_reject"] == 1 and r["status"] == status and r["t"] == t0, (t0, h0, r)
